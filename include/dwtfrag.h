@@ -1,0 +1,133 @@
+/*
+ * dwtfrag: DWT fragmentation protect / restore on one MI355X (gfx950).
+ *
+ * Method (Qiu Han, "An Efficient Data Protection Architecture Based on
+ * Fragmentation and Encryption", arXiv 1803.04880):
+ *   - Ch. 5 section 5.2.1: any byte buffer is viewed as a 2-D matrix of bytes.
+ *   - Ch. 5 section 5.1.1, eqs. (5.1)-(5.2): integer LeGall 5/3 lifting,
+ *     horizontal pass then vertical pass, dyadic levels on LL.  The update
+ *     step adds its floored term and the signal is extended whole-sample
+ *     symmetrically at every level (both fixed by matrix A and F(4,4) of
+ *     section 5.2.2.2).
+ *   - Ch. 5 sections 5.1.1 / 5.2.1 and Ch. 2 "Our SE approach": the last LL
+ *     band is the private fragment, encrypted with AES-128; the detail bands
+ *     are the public fragment.  Ch. 2 "Performance issue of SE" names counter
+ *     mode as the parallel AES mode; Ch. 5 "Cryptanalysis Discussion" suggests
+ *     a per-chunk IV, which is the nonce here.
+ *   - Ch. 5 section 5.2.3: the map is integer-to-integer and invertible, so
+ *     restore is exact.
+ *
+ * Data layout (all multi-byte values little-endian):
+ *   view      H = ceil(n / width) rows of `width` bytes, row-major; the tail of
+ *             the last row is zero padding, transformed like data.
+ *   levels    (h_0, w_0) = (H, width); (h_l, w_l) = (ceil(h_{l-1}/2),
+ *             ceil(w_{l-1}/2)).  Level l splits the h_{l-1} x w_{l-1} LL into
+ *             LL_l (h_l x w_l), HL_l (h_l x (w_{l-1}-w_l)), LH_l ((h_{l-1}-h_l)
+ *             x w_l), HH_l ((h_{l-1}-h_l) x (w_{l-1}-w_l)); HL is the
+ *             horizontal-high / vertical-low band.
+ *   priv      AES-128-CTR(key, nonce) of LL_L as int16, row-major:
+ *             priv_bytes = 2 * h_L * w_L.  Keystream block j encrypts the
+ *             counter (nonce + j) mod 2^128, nonce read as a big-endian
+ *             128-bit integer; the last block is truncated.
+ *   pub       int16 bands, for l = L down to 1: HL_l | LH_l | HH_l, each
+ *             row-major: pub_bytes = 2 * (H * width - h_L * w_L).
+ *
+ * Conventions for every entry point below:
+ *   - data pointers are DEVICE pointers (HBM of the current HIP device);
+ *     key / nonce are HOST pointers, read before the call returns.
+ *   - work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
+ *     and the call returns without waiting; results are valid once the
+ *     stream has reached that point.
+ *   - the caller owns every buffer.  The library allocates no device memory.
+ *   - arguments are validated before anything is launched; on an error
+ *     return nothing has been written.
+ *   - input and output buffers must not overlap.
+ *   - calls may come from several host threads; there is no mutable global
+ *     state besides per-device constant tables set up on first use.
+ */
+#ifndef DWTFRAG_H
+#define DWTFRAG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DWTFRAG_OK = 0,
+  DWTFRAG_EINVAL = -1,     /* null pointer, n == 0, width == 0, levels == 0 or > 32 */
+  DWTFRAG_ERANGE = -2,     /* rows or width above 2^31-1, or a byte count overflows */
+  DWTFRAG_EDEVICE = -3,    /* a HIP call or kernel launch failed */
+  DWTFRAG_EWORKSPACE = -4  /* workspace missing or smaller than workspace_bytes */
+} dwtfrag_status;
+
+/* Geometry of one buffer; filled by dwtfrag_geometry. */
+typedef struct {
+  uint64_t n;               /* buffer length in bytes */
+  uint32_t width;           /* row width W */
+  uint32_t height;          /* H = ceil(n / W) */
+  uint32_t levels;          /* L */
+  uint32_t ll_h, ll_w;      /* h_L, w_L */
+  uint64_t priv_bytes;      /* 2 * h_L * w_L */
+  uint64_t pub_bytes;       /* 2 * (H * W - h_L * w_L) */
+  uint64_t workspace_bytes; /* device scratch needed by protect / restore (0 if L <= 4) */
+} dwtfrag_geom;
+
+/* Optional launch shape (0 in a field = library default).  Results do not
+ * depend on it; it only trades parallelism against halo recomputation. */
+typedef struct {
+  uint32_t seg_rows;        /* rows owned by one wavefront (rounded up to 2^levels) */
+  uint32_t lane_cols;       /* columns per lane at level 1: 8 or 16 (16 needed for 4 levels) */
+} dwtfrag_launch;
+
+/* Host-only, pure: geometry of an n-byte buffer viewed with row width `width`
+ * and transformed over `levels` levels (Ch. 5 section 5.2.1 view, section
+ * 5.1.1 dyadic levels).  Returns DWTFRAG_OK, DWTFRAG_EINVAL or DWTFRAG_ERANGE. */
+int dwtfrag_geometry(uint64_t n, uint32_t width, uint32_t levels, dwtfrag_geom *out);
+
+/* Host-only, pure: min(4096, smallest power of two >= ceil(sqrt(n))), the row
+ * width used for batches of uneven buffers; 0 for n == 0. */
+uint32_t dwtfrag_default_width(uint64_t n);
+
+/* Forward path: view -> L-level 5/3 lifting -> priv = AES-128-CTR(LL_L),
+ * pub = detail bands (layout above).
+ *   in        device, n bytes
+ *   priv      device, geom.priv_bytes bytes (written)
+ *   pub       device, geom.pub_bytes / 2 int16 values (written); may be NULL
+ *             when pub_bytes is 0 (a 1 x 1 view)
+ *   workspace device scratch of at least geom.workspace_bytes bytes when
+ *             that is non-zero (levels > 4), else may be NULL
+ *   launch    NULL for the default launch shape */
+int dwtfrag_protect(const uint8_t *in, uint64_t n, uint32_t width, uint32_t levels,
+                    const uint8_t key[16], const uint8_t nonce[16],
+                    uint8_t *priv, int16_t *pub,
+                    void *workspace, uint64_t workspace_bytes,
+                    const dwtfrag_launch *launch, void *stream);
+
+/* Inverse path (Ch. 5 section 5.2.3, exact inverse): decrypt priv with the
+ * same keystream, inverse lifting levels L..1 (vertical then horizontal
+ * within a level), write the first n bytes; every reconstructed sample is
+ * stored modulo 256, so tampered fragments still produce n bytes.
+ *   priv, pub fragments as produced by dwtfrag_protect (device, read only)
+ *   out       device, n bytes (written) */
+int dwtfrag_restore(const uint8_t *priv, const int16_t *pub, uint64_t n, uint32_t width,
+                    uint32_t levels, const uint8_t key[16], const uint8_t nonce[16],
+                    uint8_t *out, void *workspace, uint64_t workspace_bytes,
+                    const dwtfrag_launch *launch, void *stream);
+
+/* AES-128-CTR on its own (Ch. 2 "Performance issue of SE": counter mode):
+ * out[i] = in[i] ^ keystream[16 * first_block + i] for i < nbytes, keystream
+ * block j = AES_K((nonce + j) mod 2^128).  in and out (device) may be equal. */
+int dwtfrag_aes128_ctr(const uint8_t *in, uint8_t *out, uint64_t nbytes,
+                       const uint8_t key[16], const uint8_t nonce[16],
+                       uint64_t first_block, void *stream);
+
+/* Static text for a status code. */
+const char *dwtfrag_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DWTFRAG_H */

@@ -1,0 +1,301 @@
+// C ABI of the library: validation, geometry, AES key schedule, stage and
+// launch planning.  Declarations and contracts are in include/dwtfrag.h.
+#include "dwtfrag.h"
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace dwtfrag {
+
+hipError_t launch_fwd(int L, int C1, bool u8in, const void *in, int16_t *pub, int16_t *llout,
+                      const StageParams &P, hipStream_t s);
+hipError_t launch_inv(int L, int C1, bool u8out, const int16_t *llin, const int16_t *pub,
+                      void *out, const StageParams &P, hipStream_t s);
+hipError_t launch_ctr(const uint8_t *in, uint8_t *out, uint64_t nbytes, const AesKey &key,
+                      uint64_t first_block, hipStream_t s);
+
+static constexpr AesTables kHostTables = make_aes_tables();
+
+void expand_key(const uint8_t key[16], const uint8_t nonce[16], AesKey *out) {
+  // FIPS-197 key expansion, Nk = 4, Nr = 10.  Words are kept little-endian
+  // (byte 0 of a word in bits 0..7), matching the device state layout.
+  uint32_t *w = out->rk;
+  for (int i = 0; i < 4; ++i)
+    w[i] = uint32_t(key[4 * i]) | (uint32_t(key[4 * i + 1]) << 8) |
+           (uint32_t(key[4 * i + 2]) << 16) | (uint32_t(key[4 * i + 3]) << 24);
+  uint8_t rcon = 1;
+  for (int i = 4; i < 44; ++i) {
+    uint32_t t = w[i - 1];
+    if (i % 4 == 0) {
+      t = (t >> 8) | (t << 24);  // RotWord on bytes (a0 a1 a2 a3) -> (a1 a2 a3 a0)
+      t = uint32_t(kHostTables.sbox[t & 0xFF]) | (uint32_t(kHostTables.sbox[(t >> 8) & 0xFF]) << 8) |
+          (uint32_t(kHostTables.sbox[(t >> 16) & 0xFF]) << 16) |
+          (uint32_t(kHostTables.sbox[t >> 24]) << 24);
+      t ^= rcon;
+      rcon = gf_mul(rcon, 2);
+    }
+    w[i] = w[i - 4] ^ t;
+  }
+  uint64_t hi = 0, lo = 0;
+  for (int i = 0; i < 8; ++i) {
+    hi = (hi << 8) | nonce[i];
+    lo = (lo << 8) | nonce[8 + i];
+  }
+  out->nonce_hi = hi;
+  out->nonce_lo = lo;
+}
+
+namespace {
+
+constexpr uint64_t kMaxDim = 0x7FFFFFFFull;
+
+struct Geometry {
+  uint64_t n;
+  uint32_t W, H, levels;
+  std::vector<uint64_t> h, w;  // level dims 0..levels
+  uint64_t priv_bytes, pub_bytes, ws_bytes;
+  std::vector<uint64_t> ws_off;  // workspace byte offset of LL_{4(s+1)}, s = 0..stages-2
+  int stages;
+};
+
+uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
+
+int make_geometry(uint64_t n, uint32_t width, uint32_t levels, Geometry *g) {
+  if (n == 0 || width == 0 || levels == 0 || levels > 32) return DWTFRAG_EINVAL;
+  if (width > kMaxDim) return DWTFRAG_ERANGE;
+  const uint64_t H = (n + width - 1) / width;
+  if (H > kMaxDim) return DWTFRAG_ERANGE;
+  if (H * uint64_t(width) > (uint64_t(1) << 62)) return DWTFRAG_ERANGE;
+  g->n = n;
+  g->W = width;
+  g->H = uint32_t(H);
+  g->levels = levels;
+  g->h.assign(levels + 1, 0);
+  g->w.assign(levels + 1, 0);
+  g->h[0] = H;
+  g->w[0] = width;
+  for (uint32_t l = 1; l <= levels; ++l) {
+    g->h[l] = (g->h[l - 1] + 1) / 2;
+    g->w[l] = (g->w[l - 1] + 1) / 2;
+  }
+  const uint64_t ll = g->h[levels] * g->w[levels];
+  g->priv_bytes = 2 * ll;
+  g->pub_bytes = 2 * (H * width - ll);
+  g->stages = int((levels + kMaxFused - 1) / kMaxFused);
+  g->ws_off.clear();
+  uint64_t ws = 0;
+  for (int s = 0; s + 1 < g->stages; ++s) {
+    g->ws_off.push_back(ws);
+    const int lv = kMaxFused * (s + 1);
+    ws += align256(2 * g->h[lv] * g->w[lv]);
+  }
+  g->ws_bytes = ws;
+  return DWTFRAG_OK;
+}
+
+// Element offset in pub of level l's three bands (levels stored coarsest
+// first: L, L-1, ..., 1).
+void level_offsets(const Geometry &g, uint32_t l, int64_t *hl, int64_t *lh, int64_t *hh) {
+  uint64_t off = 0;
+  for (uint32_t m = g.levels; m > l; --m) off += g.h[m - 1] * g.w[m - 1] - g.h[m] * g.w[m];
+  *hl = int64_t(off);
+  *lh = int64_t(off + g.h[l] * (g.w[l - 1] - g.w[l]));
+  *hh = int64_t(off + g.h[l] * (g.w[l - 1] - g.w[l]) + (g.h[l - 1] - g.h[l]) * g.w[l]);
+}
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// Fill stage s's parameters.  forward selects the halo shape of the direction.
+int plan_stage(const Geometry &g, int s, bool forward, const dwtfrag_launch *launch,
+               const AesKey &key, StageParams *P, int *L_out, int *C1_out) {
+  std::memset(P, 0, sizeof(*P));
+  const int lv0 = kMaxFused * s;  // global level of the stage input
+  const int L = int(std::min<uint32_t>(kMaxFused, g.levels - lv0));
+  int C1 = (launch && launch->lane_cols) ? int(launch->lane_cols) : 8;
+  if (C1 != 8 && C1 != 16) return DWTFRAG_EINVAL;
+  if (L == 4) C1 = 16;
+  P->H = int32_t(g.h[lv0]);
+  P->W = int32_t(g.w[lv0]);
+  P->n_valid = (s == 0) ? int64_t(g.n) : int64_t(g.h[lv0] * g.w[lv0]);
+  for (int l = 0; l <= L; ++l) {
+    P->hdim[l] = int32_t(g.h[lv0 + l]);
+    P->wdim[l] = int32_t(g.w[lv0 + l]);
+  }
+  for (int l = 1; l <= L; ++l)
+    level_offsets(g, uint32_t(lv0 + l), &P->off_hl[l], &P->off_lh[l], &P->off_hh[l]);
+  // halos (level-0 samples of this stage): forward needs 2^(L+1)-2 before and
+  // 2^L-1 after an owned range, inverse the reverse; rows are streamed with
+  // 2^(L+1) / 2^L (forward) and 2^L / 2^L (inverse) extra rows.
+  const int big = (1 << (L + 1)) - 2, small = (1 << L) - 1;
+  const int hl = round_up(forward ? big : small, C1);
+  const int hr = round_up(forward ? small : big, C1);
+  const int span = 64 * C1;
+  if (P->W <= span) {
+    P->own_w = P->W;
+    P->n_win = 1;
+  } else {
+    P->own_w = span - hl - hr;
+    P->n_win = (P->W + P->own_w - 1) / P->own_w;
+  }
+  P->halo_l = hl;
+  P->halo_t = forward ? (1 << (L + 1)) : (1 << L);
+  P->halo_b = 1 << L;
+  const int unit = 1 << L;
+  int own_h;
+  if (launch && launch->seg_rows) {
+    own_h = round_up(int(std::min<uint32_t>(launch->seg_rows, uint32_t(P->H))), unit);
+  } else {
+    const int64_t target_waves = 4096;
+    int64_t want = (int64_t(P->H) * P->n_win + target_waves - 1) / target_waves;
+    want = std::max<int64_t>(want, 2 * unit);
+    want = std::max<int64_t>(want, std::min<int64_t>(64, P->H));
+    own_h = round_up(int(std::min<int64_t>(want, P->H)), unit);
+  }
+  own_h = std::max(own_h, unit);
+  P->own_h = own_h;
+  P->n_seg = (P->H + own_h - 1) / own_h;
+  const int64_t waves = int64_t(P->n_win) * P->n_seg;
+  if (waves > (int64_t(1) << 30)) return DWTFRAG_ERANGE;
+  P->n_waves = int32_t(waves);
+  const bool last = (s == g.stages - 1);
+  P->use_aes = last ? 1 : 0;
+  // keystream ring: LL columns per wavefront (forward: owned, inverse: lanes)
+  const int ll_cols = forward ? std::min<int>(P->wdim[L], (P->own_w >> L) + 1)
+                              : std::min<int>(P->wdim[L], span >> L);
+  P->ks_blocks = (2 * ll_cols + 30) / 16;
+  P->ks_rows = std::max(1, 64 / P->ks_blocks);
+  if (P->ks_rows * P->ks_blocks > kRingBlocks) P->ks_rows = kRingBlocks / P->ks_blocks;
+  if (P->ks_rows < 1) return DWTFRAG_ERANGE;
+  P->key = key;
+  *L_out = L;
+  *C1_out = C1;
+  return DWTFRAG_OK;
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+}  // namespace
+}  // namespace dwtfrag
+
+using namespace dwtfrag;
+
+extern "C" {
+
+int dwtfrag_geometry(uint64_t n, uint32_t width, uint32_t levels, dwtfrag_geom *out) {
+  if (!out) return DWTFRAG_EINVAL;
+  Geometry g;
+  const int rc = make_geometry(n, width, levels, &g);
+  if (rc != DWTFRAG_OK) return rc;
+  out->n = n;
+  out->width = width;
+  out->height = g.H;
+  out->levels = levels;
+  out->ll_h = uint32_t(g.h[levels]);
+  out->ll_w = uint32_t(g.w[levels]);
+  out->priv_bytes = g.priv_bytes;
+  out->pub_bytes = g.pub_bytes;
+  out->workspace_bytes = g.ws_bytes;
+  return DWTFRAG_OK;
+}
+
+uint32_t dwtfrag_default_width(uint64_t n) {
+  if (n == 0) return 0;
+  uint64_t r = 1;
+  while (r * r < n) r <<= 1;  // smallest power of two whose square reaches n
+  // r is now the smallest power of two >= sqrt(n); that equals the smallest
+  // power of two >= ceil(sqrt(n)).
+  return uint32_t(std::min<uint64_t>(4096, r));
+}
+
+int dwtfrag_protect(const uint8_t *in, uint64_t n, uint32_t width, uint32_t levels,
+                    const uint8_t key[16], const uint8_t nonce[16], uint8_t *priv, int16_t *pub,
+                    void *workspace, uint64_t workspace_bytes, const dwtfrag_launch *launch,
+                    void *stream) {
+  if (!in || !key || !nonce || !priv) return DWTFRAG_EINVAL;
+  Geometry g;
+  int rc = make_geometry(n, width, levels, &g);
+  if (rc != DWTFRAG_OK) return rc;
+  if (!pub && g.pub_bytes) return DWTFRAG_EINVAL;  // pub may be NULL only when empty
+  if (g.ws_bytes && (!workspace || workspace_bytes < g.ws_bytes)) return DWTFRAG_EWORKSPACE;
+  if (!aligned16(in) || !aligned16(priv) || !aligned16(pub) || (workspace && !aligned16(workspace)))
+    return DWTFRAG_EINVAL;
+  AesKey k;
+  expand_key(key, nonce, &k);
+  std::vector<StageParams> plans(g.stages);
+  std::vector<int> Ls(g.stages), C1s(g.stages);
+  for (int s = 0; s < g.stages; ++s) {
+    rc = plan_stage(g, s, true, launch, k, &plans[s], &Ls[s], &C1s[s]);
+    if (rc != DWTFRAG_OK) return rc;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int s = 0; s < g.stages; ++s) {
+    const bool last = (s == g.stages - 1);
+    const void *src = (s == 0) ? static_cast<const void *>(in)
+                               : static_cast<const char *>(workspace) + g.ws_off[s - 1];
+    int16_t *dst = last ? reinterpret_cast<int16_t *>(priv)
+                        : reinterpret_cast<int16_t *>(static_cast<char *>(workspace) + g.ws_off[s]);
+    if (launch_fwd(Ls[s], C1s[s], s == 0, src, pub, dst, plans[s], st) != hipSuccess)
+      return DWTFRAG_EDEVICE;
+  }
+  return DWTFRAG_OK;
+}
+
+int dwtfrag_restore(const uint8_t *priv, const int16_t *pub, uint64_t n, uint32_t width,
+                    uint32_t levels, const uint8_t key[16], const uint8_t nonce[16], uint8_t *out,
+                    void *workspace, uint64_t workspace_bytes, const dwtfrag_launch *launch,
+                    void *stream) {
+  if (!priv || !key || !nonce || !out) return DWTFRAG_EINVAL;
+  Geometry g;
+  int rc = make_geometry(n, width, levels, &g);
+  if (rc != DWTFRAG_OK) return rc;
+  if (!pub && g.pub_bytes) return DWTFRAG_EINVAL;  // pub may be NULL only when empty
+  if (g.ws_bytes && (!workspace || workspace_bytes < g.ws_bytes)) return DWTFRAG_EWORKSPACE;
+  if (!aligned16(out) || !aligned16(priv) || !aligned16(pub) || (workspace && !aligned16(workspace)))
+    return DWTFRAG_EINVAL;
+  AesKey k;
+  expand_key(key, nonce, &k);
+  std::vector<StageParams> plans(g.stages);
+  std::vector<int> Ls(g.stages), C1s(g.stages);
+  for (int s = 0; s < g.stages; ++s) {
+    rc = plan_stage(g, s, false, launch, k, &plans[s], &Ls[s], &C1s[s]);
+    if (rc != DWTFRAG_OK) return rc;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int s = g.stages - 1; s >= 0; --s) {
+    const bool last = (s == g.stages - 1);
+    const int16_t *src = last ? reinterpret_cast<const int16_t *>(priv)
+                              : reinterpret_cast<const int16_t *>(
+                                    static_cast<const char *>(workspace) + g.ws_off[s]);
+    void *dst = (s == 0) ? static_cast<void *>(out)
+                         : static_cast<void *>(static_cast<char *>(workspace) + g.ws_off[s - 1]);
+    if (launch_inv(Ls[s], C1s[s], s == 0, src, pub, dst, plans[s], st) != hipSuccess)
+      return DWTFRAG_EDEVICE;
+  }
+  return DWTFRAG_OK;
+}
+
+int dwtfrag_aes128_ctr(const uint8_t *in, uint8_t *out, uint64_t nbytes, const uint8_t key[16],
+                       const uint8_t nonce[16], uint64_t first_block, void *stream) {
+  if (!in || !out || !key || !nonce || nbytes == 0) return DWTFRAG_EINVAL;
+  AesKey k;
+  expand_key(key, nonce, &k);
+  if (launch_ctr(in, out, nbytes, k, first_block, static_cast<hipStream_t>(stream)) != hipSuccess)
+    return DWTFRAG_EDEVICE;
+  return DWTFRAG_OK;
+}
+
+const char *dwtfrag_strerror(int code) {
+  switch (code) {
+    case DWTFRAG_OK: return "ok";
+    case DWTFRAG_EINVAL: return "invalid argument (null or misaligned pointer, zero size, bad levels or launch shape)";
+    case DWTFRAG_ERANGE: return "geometry out of range";
+    case DWTFRAG_EDEVICE: return "HIP runtime or launch error";
+    case DWTFRAG_EWORKSPACE: return "workspace missing or too small";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

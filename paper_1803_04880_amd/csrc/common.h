@@ -1,0 +1,160 @@
+// Shared definitions of the HIP path: launch parameters, wavefront neighbour
+// taps, and AES-128 (tables derived at compile time from GF(2^8) arithmetic).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dwtfrag {
+
+// Levels fused into one streaming kernel; deeper transforms run as further
+// stages over the LL band of the previous stage.
+constexpr int kMaxFused = 4;
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlockThreads = 64 * kWavesPerBlock;
+// Keystream ring per wavefront: up to 96 AES blocks of 16 bytes.
+constexpr int kRingBlocks = 96;
+
+// ----------------------------------------------------------------- AES-128 --
+// FIPS-197 S-box: multiplicative inverse in GF(2^8) mod x^8+x^4+x^3+x+1, then
+// the affine map b_i ^ b_{i+4} ^ b_{i+5} ^ b_{i+6} ^ b_{i+7} ^ 0x63_i.
+constexpr uint8_t gf_mul(uint8_t a, uint8_t b) {
+  uint8_t r = 0;
+  for (int i = 0; i < 8; ++i) {
+    if (b & 1) r ^= a;
+    bool hi = a & 0x80;
+    a = uint8_t(a << 1);
+    if (hi) a ^= 0x1B;
+    b >>= 1;
+  }
+  return r;
+}
+
+constexpr uint8_t gf_inv(uint8_t a) {
+  if (a == 0) return 0;
+  uint8_t r = 1, base = a;
+  int e = 254;
+  while (e) {
+    if (e & 1) r = gf_mul(r, base);
+    base = gf_mul(base, base);
+    e >>= 1;
+  }
+  return r;
+}
+
+constexpr uint8_t rotl8(uint8_t v, int s) { return uint8_t((v << s) | (v >> (8 - s))); }
+
+constexpr uint8_t sbox_entry(uint8_t a) {
+  uint8_t b = gf_inv(a);
+  return uint8_t(b ^ rotl8(b, 1) ^ rotl8(b, 2) ^ rotl8(b, 3) ^ rotl8(b, 4) ^ 0x63);
+}
+
+struct AesTables {
+  uint8_t sbox[256];
+  // te0[x]: MixColumns column of a substituted byte in row 0, as a
+  // little-endian word (bytes 2S, S, S, 3S); rows 1..3 are byte rotations.
+  uint32_t te0[256];
+};
+
+constexpr AesTables make_aes_tables() {
+  AesTables t{};
+  for (int x = 0; x < 256; ++x) {
+    uint8_t s = sbox_entry(uint8_t(x));
+    uint8_t s2 = gf_mul(s, 2), s3 = uint8_t(s2 ^ s);
+    t.sbox[x] = s;
+    t.te0[x] = uint32_t(s2) | (uint32_t(s) << 8) | (uint32_t(s) << 16) | (uint32_t(s3) << 24);
+  }
+  return t;
+}
+
+// Round keys as little-endian column words (44 words); nonce as two 64-bit
+// big-endian halves.
+struct AesKey {
+  uint32_t rk[44];
+  uint64_t nonce_hi, nonce_lo;
+};
+
+void expand_key(const uint8_t key[16], const uint8_t nonce[16], AesKey *out);
+
+__device__ __forceinline__ uint32_t bswap32(uint32_t v) { return __builtin_bswap32(v); }
+
+// Block j of the counter sequence as 4 little-endian state words.
+__device__ __forceinline__ void counter_block(const AesKey &k, uint64_t j, uint32_t w[4]) {
+  uint64_t lo = k.nonce_lo + j;
+  uint64_t hi = k.nonce_hi + (lo < k.nonce_lo ? 1ull : 0ull);
+  w[0] = bswap32(uint32_t(hi >> 32));
+  w[1] = bswap32(uint32_t(hi));
+  w[2] = bswap32(uint32_t(lo >> 32));
+  w[3] = bswap32(uint32_t(lo));
+}
+
+// One AES-128 encryption; `te` points at four 256-word tables in LDS
+// (te[256 r + x] = rotl(te0[x], 8 r)).
+__device__ __forceinline__ void aes_encrypt(const uint32_t *te, const AesKey &k, uint32_t w[4]) {
+  uint32_t s0 = w[0] ^ k.rk[0], s1 = w[1] ^ k.rk[1], s2 = w[2] ^ k.rk[2], s3 = w[3] ^ k.rk[3];
+#define DWTFRAG_TE(r, v) te[256 * (r) + (((v) >> (8 * (r))) & 0xFF)]
+#pragma unroll
+  for (int rnd = 1; rnd < 10; ++rnd) {
+    uint32_t t0 = DWTFRAG_TE(0, s0) ^ DWTFRAG_TE(1, s1) ^ DWTFRAG_TE(2, s2) ^ DWTFRAG_TE(3, s3) ^ k.rk[4 * rnd + 0];
+    uint32_t t1 = DWTFRAG_TE(0, s1) ^ DWTFRAG_TE(1, s2) ^ DWTFRAG_TE(2, s3) ^ DWTFRAG_TE(3, s0) ^ k.rk[4 * rnd + 1];
+    uint32_t t2 = DWTFRAG_TE(0, s2) ^ DWTFRAG_TE(1, s3) ^ DWTFRAG_TE(2, s0) ^ DWTFRAG_TE(3, s1) ^ k.rk[4 * rnd + 2];
+    uint32_t t3 = DWTFRAG_TE(0, s3) ^ DWTFRAG_TE(1, s0) ^ DWTFRAG_TE(2, s1) ^ DWTFRAG_TE(3, s2) ^ k.rk[4 * rnd + 3];
+    s0 = t0; s1 = t1; s2 = t2; s3 = t3;
+  }
+#undef DWTFRAG_TE
+  // last round: SubBytes + ShiftRows only; S[x] is byte 1 of te0[x]
+#define DWTFRAG_S(v, r) ((te[((v) >> (8 * (r))) & 0xFF] >> 8) & 0xFF)
+  w[0] = (DWTFRAG_S(s0, 0) | (DWTFRAG_S(s1, 1) << 8) | (DWTFRAG_S(s2, 2) << 16) | (DWTFRAG_S(s3, 3) << 24)) ^ k.rk[40];
+  w[1] = (DWTFRAG_S(s1, 0) | (DWTFRAG_S(s2, 1) << 8) | (DWTFRAG_S(s3, 2) << 16) | (DWTFRAG_S(s0, 3) << 24)) ^ k.rk[41];
+  w[2] = (DWTFRAG_S(s2, 0) | (DWTFRAG_S(s3, 1) << 8) | (DWTFRAG_S(s0, 2) << 16) | (DWTFRAG_S(s1, 3) << 24)) ^ k.rk[42];
+  w[3] = (DWTFRAG_S(s3, 0) | (DWTFRAG_S(s0, 1) << 8) | (DWTFRAG_S(s1, 2) << 16) | (DWTFRAG_S(s2, 3) << 24)) ^ k.rk[43];
+#undef DWTFRAG_S
+}
+
+static __constant__ AesTables c_aes = make_aes_tables();
+
+// Fill the four rotated tables (1024 words) cooperatively; caller syncs.
+__device__ __forceinline__ void load_aes_tables(uint32_t *te) {
+  for (int i = threadIdx.x; i < 1024; i += blockDim.x) {
+    const uint32_t v = c_aes.te0[i & 255];
+    const int r = 8 * (i >> 8);
+    te[i] = r ? ((v << r) | (v >> (32 - r))) : v;
+  }
+}
+
+// --------------------------------------------------------- launch geometry --
+// One stage = up to kMaxFused levels over an H x W input.  Wavefronts own
+// rectangles of the level-0 grid: window k owns columns [k*own_w, ...),
+// segment s owns rows [s*own_h, ...).
+struct StageParams {
+  int64_t n_valid;            // valid input elements (byte view: n; else H*W)
+  int32_t H, W;               // stage input dims
+  int32_t hdim[kMaxFused + 1], wdim[kMaxFused + 1];  // level dims, [0] = input
+  int64_t off_hl[kMaxFused + 1], off_lh[kMaxFused + 1], off_hh[kMaxFused + 1];
+  int32_t own_w, n_win;       // owned columns per window, number of windows
+  int32_t own_h, n_seg;       // owned rows per segment, number of segments
+  int32_t halo_l;             // columns before the owned range (multiple of lane_cols)
+  int32_t halo_t, halo_b;     // rows streamed before / after the owned range
+  int32_t n_waves;
+  int32_t use_aes;            // LL output / input goes through AES-CTR
+  int32_t ks_rows, ks_blocks; // keystream ring: rows per refill, blocks per row
+  AesKey key;
+};
+
+// ------------------------------------------------------- wavefront taps --
+// wave_shl:1 -> lane i receives lane i+1; wave_shr:1 -> lane i receives
+// lane i-1 (the lane with no source receives 0).
+__device__ __forceinline__ int from_next_lane(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int from_prev_lane(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace dwtfrag

@@ -1,0 +1,239 @@
+// Inverse path: AES-CTR decryption of the LL band fused with the multi-level
+// inverse 5/3 lifting, as one streaming kernel (Ch. 5 section 5.2.3: the map
+// is an invertible integer-to-integer map, so restore is exact).
+//
+// Within a level the vertical pass is undone first, then the horizontal one
+// (the reverse of the forward order).  A wavefront streams the LL rows of the
+// coarsest level; a step of level l consumes LL_l row k together with the
+// detail rows k of HL_l / LH_l / HH_l and emits rows 2k-1 and 2k of the
+// level-(l-1) grid, which are inverted horizontally and become LL_(l-1) rows
+// for level l-1.  Level 1 emits output rows.
+#include "lift.h"
+
+namespace dwtfrag {
+
+template <int L, int C1, bool U8OUT>
+struct InvWave {
+  template <int l> static constexpr int C = C1 >> (l - 1);
+
+  const StageParams &P;
+  const int16_t *llin;     // LL_L (priv bytes or int16 scratch)
+  const int16_t *pub;
+  uint8_t *out8;
+  int16_t *out16;
+  KsRing ks;
+  int lane;
+  int c0;
+  int X0, Y0, X1, Y1;
+  bool last_win, last_seg;
+
+  int Dp1[C<1>], Xp1[C<1>];
+  int Dp2[C1 >= 2 ? C<2> : 1], Xp2[C1 >= 2 ? C<2> : 1];
+  int Dp3[C1 >= 4 ? C<3> : 1], Xp3[C1 >= 4 ? C<3> : 1];
+  int Dp4[C1 >= 8 ? C<4> : 1], Xp4[C1 >= 8 ? C<4> : 1];
+  int k0[kMaxFused + 1];   // first step index of each level's stream
+  bool hedge[kMaxFused + 1];
+
+  template <int l> __device__ auto &Dp() {
+    if constexpr (l == 1) return Dp1; else if constexpr (l == 2) return Dp2;
+    else if constexpr (l == 3) return Dp3; else return Dp4;
+  }
+  template <int l> __device__ auto &Xp() {
+    if constexpr (l == 1) return Xp1; else if constexpr (l == 2) return Xp2;
+    else if constexpr (l == 3) return Xp3; else return Xp4;
+  }
+
+  // Row i of the level-(l-1) grid after the vertical inverse of level l:
+  // undo the horizontal pass, then hand it down.
+  template <int l> __device__ __forceinline__ void emit_row(int (&x)[C<l>], int i) {
+    constexpr int CC = C<l>;
+    hinv_any<CC>(x, c0 >> (l - 1), P.wdim[l - 1], hedge[l]);
+    if constexpr (l > 1) {
+      push_ll<l - 1>(x, i);
+    } else {
+      if (i < Y0 || (!last_seg && i >= Y1)) return;
+      if (c0 < X0 || (!last_win && c0 >= X1)) return;
+      const int64_t idx = int64_t(i) * P.W + c0;
+      if constexpr (U8OUT) {
+        const int64_t lim = min(int64_t(P.W - c0), P.n_valid - int64_t(i) * P.W);
+        if (lim >= C1 && (idx & (C1 - 1)) == 0) {
+          uint32_t w[C1 / 4];
+#pragma unroll
+          for (int q = 0; q < C1 / 4; ++q)
+            w[q] = (uint32_t(x[4 * q]) & 0xFFu) | ((uint32_t(x[4 * q + 1]) & 0xFFu) << 8) |
+                   ((uint32_t(x[4 * q + 2]) & 0xFFu) << 16) | (uint32_t(x[4 * q + 3]) << 24);
+          if constexpr (C1 == 8) *reinterpret_cast<uint2 *>(out8 + idx) = make_uint2(w[0], w[1]);
+          else *reinterpret_cast<uint4 *>(out8 + idx) = make_uint4(w[0], w[1], w[2], w[3]);
+        } else {
+#pragma unroll
+          for (int t = 0; t < C1; ++t)
+            if (t < lim) out8[idx + t] = uint8_t(x[t]);
+        }
+      } else {
+        store_i16<C1>(out16, idx, P.W - c0, x);
+      }
+    }
+  }
+
+  // Step k of level l: LL_l row k arrives (values of this lane's LL columns).
+  // The step yields up to three rows of the level-(l-1) grid (2k-1, 2k and,
+  // at the end of an even-length signal, 2k+1), emitted from one call site.
+  template <int l> __device__ __forceinline__ void push_ll(const int (&ll)[C<l> / 2], int k) {
+    constexpr int CC = C<l>;
+    constexpr int U = CC / 2;
+    const int N = P.hdim[l - 1];
+    const int Nw = P.wdim[l - 1];
+    const int wl = P.wdim[l];
+    const int bc = c0 >> l;
+    int hl[U];
+    load_i16<U>(pub + P.off_hl[l], int64_t(k) * (Nw - wl) + bc, (Nw - wl) - bc, hl);
+    int S[CC];
+#pragma unroll
+    for (int u = 0; u < U; ++u) { S[2 * u] = ll[u]; S[2 * u + 1] = hl[u]; }
+    auto &Dv = Dp<l>();
+    auto &Xv = Xp<l>();
+    int R0[CC], R1[CC], R2[CC];
+    int e_begin = 1, e_end = 2;
+    if (N == 1) {  // no vertical pass at this level: the row is row 0
+#pragma unroll
+      for (int t = 0; t < CC; ++t) R1[t] = S[t];
+    } else {
+      int Dn[CC];
+      const bool has_d = (2 * k + 1 < N);
+      if (has_d) {
+        int lh[U], hh[U];
+        load_i16<U>(pub + P.off_lh[l], int64_t(k) * wl + bc, wl - bc, lh);
+        load_i16<U>(pub + P.off_hh[l], int64_t(k) * (Nw - wl) + bc, (Nw - wl) - bc, hh);
+#pragma unroll
+        for (int u = 0; u < U; ++u) { Dn[2 * u] = lh[u]; Dn[2 * u + 1] = hh[u]; }
+      } else {  // odd length, last step: d(N) = d(N-2)
+#pragma unroll
+        for (int t = 0; t < CC; ++t) Dn[t] = Dv[t];
+      }
+      const bool top = (k == 0);
+#pragma unroll
+      for (int t = 0; t < CC; ++t) {
+        const int X = S[t] - (((top ? Dn[t] : Dv[t]) + Dn[t] + 2) >> 2);
+        R0[t] = Dv[t] + ((Xv[t] + X) >> 1);  // x(2k-1)
+        R1[t] = X;                             // x(2k)
+        R2[t] = Dn[t] + X;                     // x(2k+1) when 2k+1 == N-1
+        Dv[t] = Dn[t];
+        Xv[t] = X;
+      }
+      if (k != k0[l]) e_begin = 0;
+      if (2 * k + 1 == N - 1) e_end = 3;
+    }
+#pragma unroll 1
+    for (int e = e_begin; e < e_end; ++e) {
+      int row[CC];
+#pragma unroll
+      for (int t = 0; t < CC; ++t) row[t] = e == 0 ? R0[t] : (e == 1 ? R1[t] : R2[t]);
+      emit_row<l>(row, 2 * k - 1 + e);
+    }
+  }
+
+  __device__ __forceinline__ void load_ll(int k, int (&ll)[C<L> / 2]) {
+    constexpr int U = C<L> / 2;
+    const int wl = P.wdim[L];
+    const int bc = c0 >> L;
+    load_i16<U>(llin, int64_t(k) * wl + bc, wl - bc, ll);
+  }
+
+  __device__ __forceinline__ void run(int wave) {
+    const int win = wave % P.n_win;
+    const int seg = wave / P.n_win;
+    X0 = win * P.own_w;
+    Y0 = seg * P.own_h;
+    last_win = (win == P.n_win - 1);
+    last_seg = (seg == P.n_seg - 1);
+    X1 = last_win ? P.W : X0 + P.own_w;
+    Y1 = last_seg ? P.H : Y0 + P.own_h;
+    const int cbase = (win == 0) ? 0 : X0 - P.halo_l;
+    c0 = cbase + lane * C1;
+    const int kbeg = (Y0 > P.halo_t ? Y0 - P.halo_t : 0) >> L;
+    const int kend = min(P.hdim[L], (Y1 + P.halo_b) >> L);
+#pragma unroll
+    for (int l = 1; l <= L; ++l) {
+      k0[l] = kbeg << (L - l);
+      const int N = P.wdim[l - 1];
+      const int j0 = cbase >> (l - 1);
+      const int span = (64 * C1) >> (l - 1);
+      hedge[l] = (j0 == 0) || (N - 1 >= j0 && N - 1 < j0 + span);
+    }
+    for (int t = 0; t < C<1>; ++t) { Dp1[t] = 0; Xp1[t] = 0; }
+    for (int t = 0; t < (C1 >= 2 ? C<2> : 1); ++t) { Dp2[t] = 0; Xp2[t] = 0; }
+    for (int t = 0; t < (C1 >= 4 ? C<3> : 1); ++t) { Dp3[t] = 0; Xp3[t] = 0; }
+    for (int t = 0; t < (C1 >= 8 ? C<4> : 1); ++t) { Dp4[t] = 0; Xp4[t] = 0; }
+    ks.col_lo = min(P.wdim[L], cbase >> L);
+    ks.col_hi = min(P.wdim[L], (cbase + 64 * C1) >> L);
+    ks.wL = P.wdim[L];
+    ks.base = -1;
+
+    if (kbeg >= kend) return;
+    constexpr int U = C<L> / 2;
+    int nxt[U];
+    load_ll(kbeg, nxt);
+    for (int k = kbeg; k < kend; ++k) {
+      int cur[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+      if (k + 1 < kend) load_ll(k + 1, nxt);
+      if (P.use_aes) {
+        ks.ensure(k, kend, P.key, lane);
+        const int nv = P.wdim[L] - (c0 >> L);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (u < nv) cur[u] = int(int16_t(uint16_t(cur[u]) ^ uint16_t(ks.ks16(k, (c0 >> L) + u))));
+      }
+      push_ll<L>(cur, k);
+    }
+  }
+};
+
+template <int L, int C1, bool U8OUT>
+__global__ __launch_bounds__(kBlockThreads) void inv_kernel(const int16_t *__restrict__ llin,
+                                                            const int16_t *__restrict__ pub,
+                                                            void *__restrict__ out,
+                                                            const StageParams P) {
+  __shared__ uint32_t s_te[1024];
+  __shared__ uint32_t s_ring[kWavesPerBlock][kRingBlocks * 4];
+  if (P.use_aes) load_aes_tables(s_te);
+  __syncthreads();
+  const int wib = threadIdx.x >> 6;
+  const int wave = blockIdx.x * kWavesPerBlock + wib;
+  if (wave >= P.n_waves) return;
+  InvWave<L, C1, U8OUT> w{P};
+  w.llin = llin;
+  w.pub = pub;
+  w.out8 = static_cast<uint8_t *>(out);
+  w.out16 = static_cast<int16_t *>(out);
+  w.lane = threadIdx.x & 63;
+  w.ks.ring = s_ring[wib];
+  w.ks.te = s_te;
+  w.ks.rows = P.ks_rows;
+  w.ks.blocks = P.ks_blocks;
+  w.run(wave);
+}
+
+template <int L, int C1, bool U8OUT>
+static hipError_t launch_inv_t(const int16_t *llin, const int16_t *pub, void *out,
+                               const StageParams &P, hipStream_t s) {
+  const int blocks = (P.n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
+  hipLaunchKernelGGL((inv_kernel<L, C1, U8OUT>), dim3(blocks), dim3(kBlockThreads), 0, s, llin,
+                     pub, out, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_inv(int L, int C1, bool u8out, const int16_t *llin, const int16_t *pub,
+                      void *out, const StageParams &P, hipStream_t s) {
+#define DWTFRAG_CASE(LL, CC)                                                   \
+  if (L == LL && C1 == CC)                                                     \
+    return u8out ? launch_inv_t<LL, CC, true>(llin, pub, out, P, s)            \
+                 : launch_inv_t<LL, CC, false>(llin, pub, out, P, s);
+  DWTFRAG_CASE(1, 8) DWTFRAG_CASE(2, 8) DWTFRAG_CASE(3, 8)
+  DWTFRAG_CASE(1, 16) DWTFRAG_CASE(2, 16) DWTFRAG_CASE(3, 16) DWTFRAG_CASE(4, 16)
+#undef DWTFRAG_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dwtfrag

@@ -1,0 +1,118 @@
+"""Host-side checks of the C ABI (no GPU needed, no kernel launched).
+
+* the library loads and exports every function include/dwtfrag.h declares;
+* geometry and default width agree with the oracle's bookkeeping;
+* invalid arguments return the documented status codes before any launch.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+from oracle import fragment
+
+pkg = pytest.importorskip("paper_1803_04880_amd")
+
+HEADER = os.path.join(ROOT, "include", "dwtfrag.h")
+
+
+def _lib_or_skip():
+    if not os.path.exists(pkg.LIB_PATH):
+        pytest.skip("libdwtfrag.so not built")
+    return pkg.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dwtfrag_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    assert declared_functions() == sorted(pkg.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib_or_skip()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    nm = os.popen(f"nm -D --defined-only {pkg.LIB_PATH}").read()
+    for name in declared_functions():
+        assert re.search(rf"\bT {name}\b", nm), name
+
+
+@pytest.mark.parametrize("n,width,levels", [
+    (1, 1, 1), (7, 3, 2), (262144, 512, 1), (1 << 28, 32768, 3), (100003, 317, 3),
+    (5000, 1, 4), (5000, 5000, 4), (12345, 64, 6), (1 << 20, 1024, 9), (3, 2, 32),
+])
+def test_geometry_matches_oracle(n, width, levels):
+    _lib_or_skip()
+    g = pkg.geometry(n, width, levels)
+    o = fragment.geometry(n, width, levels)
+    assert g["height"] == o["height"]
+    assert (g["ll_h"], g["ll_w"]) == (o["ll_h"], o["ll_w"])
+    assert g["priv_bytes"] == o["priv_bytes"] and g["pub_bytes"] == o["pub_bytes"]
+    assert (g["workspace_bytes"] > 0) == (levels > 4)
+
+
+def test_default_width_matches_oracle():
+    _lib_or_skip()
+    for n in list(range(1, 300)) + [4095, 4096, 4097, 1 << 24, (1 << 24) + 1, 1 << 26, 10 ** 9]:
+        assert pkg.default_width(n) == fragment.default_width(n), n
+    assert pkg.default_width(0) == 0
+
+
+def test_geometry_errors():
+    L = _lib_or_skip()
+    g = pkg._Geom()
+    assert L.dwtfrag_geometry(0, 4, 1, ctypes.byref(g)) == pkg.DWTFRAG_EINVAL
+    assert L.dwtfrag_geometry(10, 0, 1, ctypes.byref(g)) == pkg.DWTFRAG_EINVAL
+    assert L.dwtfrag_geometry(10, 4, 0, ctypes.byref(g)) == pkg.DWTFRAG_EINVAL
+    assert L.dwtfrag_geometry(10, 4, 33, ctypes.byref(g)) == pkg.DWTFRAG_EINVAL
+    assert L.dwtfrag_geometry(10, 4, 1, None) == pkg.DWTFRAG_EINVAL
+    assert L.dwtfrag_geometry(10, 1 << 31, 1, ctypes.byref(g)) == pkg.DWTFRAG_ERANGE
+    assert L.dwtfrag_geometry(1 << 40, 1, 1, ctypes.byref(g)) == pkg.DWTFRAG_ERANGE
+
+
+def test_protect_restore_reject_bad_arguments_before_launch():
+    L = _lib_or_skip()
+    key = b"k" * 16
+    fake = ctypes.c_void_p(0x10000)  # never dereferenced: validation fails first
+    bad = [
+        (None, 100, 10, 1, key, key, fake, fake, None, 0, None, None),   # null input
+        (fake, 0, 10, 1, key, key, fake, fake, None, 0, None, None),     # n == 0
+        (fake, 100, 0, 1, key, key, fake, fake, None, 0, None, None),    # width == 0
+        (fake, 100, 10, 0, key, key, fake, fake, None, 0, None, None),   # levels == 0
+        (fake, 100, 10, 33, key, key, fake, fake, None, 0, None, None),  # levels > 32
+        (fake, 100, 10, 1, None, key, fake, fake, None, 0, None, None),  # null key
+        (ctypes.c_void_p(0x10001), 100, 10, 1, key, key, fake, fake, None, 0, None, None),
+    ]
+    for args in bad:
+        assert L.dwtfrag_protect(*args) == pkg.DWTFRAG_EINVAL
+    # levels > 4 needs a workspace
+    assert L.dwtfrag_protect(fake, 100000, 300, 6, key, key, fake, fake, None, 0, None,
+                             None) == pkg.DWTFRAG_EWORKSPACE
+    assert L.dwtfrag_restore(fake, fake, 100000, 300, 6, key, key, fake, None, 0, None,
+                             None) == pkg.DWTFRAG_EWORKSPACE
+    assert L.dwtfrag_restore(None, fake, 100, 10, 1, key, key, fake, None, 0, None,
+                             None) == pkg.DWTFRAG_EINVAL
+    assert L.dwtfrag_restore(fake, fake, 100, 10, 1, key, key, None, None, 0, None,
+                             None) == pkg.DWTFRAG_EINVAL
+    bad_launch = pkg.Launch(0, 12)
+    assert L.dwtfrag_protect(fake, 100, 10, 1, key, key, fake, fake, None, 0,
+                             ctypes.byref(bad_launch), None) == pkg.DWTFRAG_EINVAL
+    assert L.dwtfrag_aes128_ctr(fake, fake, 0, key, key, 0, None) == pkg.DWTFRAG_EINVAL
+    for code in (0, -1, -2, -3, -4, 7):
+        assert pkg.strerror(code)
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The package never imports the oracle (or any CPU fallback)."""
+    pdir = os.path.join(ROOT, "paper_1803_04880_amd")
+    for dirpath, _, files in os.walk(pdir):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in re.sub(r"#.*|//.*", "", text), f
