@@ -1,0 +1,250 @@
+"""Benchmark: protect + restore throughput on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config large|small]
+
+A step is one pass of the whole hot path over the workload: protect (view,
+3-level 5/3 lifting, band scatter, AES-CTR of LL) then restore (AES-CTR,
+inverse lifting, byte store), inputs resident in HBM.  Prints one JSON line.
+
+value      = n * K / (wall time of K steps)               [GB/s of user bytes]
+roofline   = algorithmic bytes per launch (n + 2*H*W: read the bytes, write
+             the int16 fragments; restore reads them back and writes bytes)
+             / average launch duration of the dominant kernel, against
+             8 TB/s HBM peak.  Durations come from HIP events recorded on the
+             stream the kernels run on.
+cpu_baseline = the CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    lo, hi = int(k), min(int(k) + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def source_hash() -> str:
+    """Hash of the kernel sources; stored HBM-traffic figures are only used
+    while it matches the one recorded with them."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1803_04880_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload_key: str):
+    path = os.path.join(PROFILES, "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec.get(workload_key)
+
+
+def cpu_baseline(cfg, rows: int = 512, row0: int = 2560):
+    """Oracle protect + restore on `rows` rows of the workload (one process)."""
+    import numpy as np
+    from oracle import fragment
+    w, lv = cfg["width"], cfg["levels"]
+    sample = np.ascontiguousarray(cfg["buf"][row0 * w:(row0 + rows) * w])
+    t0 = time.perf_counter()
+    priv, pub = fragment.protect(sample, w, lv, cfg["key"], cfg["nonce"])
+    back = fragment.restore(priv, pub, sample.size, w, lv, cfg["key"], cfg["nonce"])
+    dt = time.perf_counter() - t0
+    assert back == sample.tobytes()
+    return dict(value=round(sample.size / dt / 1e9, 4), unit="GB/s", cores=1, kind="oracle",
+                sample=f"rows {row0}..{row0 + rows} of the {w}-wide workload "
+                       f"({sample.size / 2**20:.0f} MiB, {lv} levels), protect+restore, "
+                       f"NumPy oracle in one process, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", choices=["large", "small"], default="large")
+    ap.add_argument("--seg-rows", type=int, default=0)
+    ap.add_argument("--lane-cols", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="no timing: 2 plain device copies of n bytes (counter calibration), "
+                         "then 2 protect and 2 restore launches, for rocprofv3")
+    ap.add_argument("--cold", action="store_true",
+                    help="also time each direction after overwriting 1 GiB (cache cold)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(each buffer is independent; see the design notes on sharding).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1803_04880_amd as dwtfrag
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    cfg = synth.config_large() if args.config == "large" else synth.config_small()
+    buf = cfg["buf"]
+    n, width, levels, key, nonce = buf.size, cfg["width"], cfg["levels"], cfg["key"], cfg["nonce"]
+    log(f"workload {cfg['name']}: n={n} generated in {time.time() - t0:.1f}s")
+    g = dwtfrag.geometry(n, width, levels)
+    H = g["height"]
+    launch = dwtfrag.Launch(args.seg_rows, args.lane_cols) if (args.seg_rows or args.lane_cols) else None
+
+    x = torch.from_numpy(buf).to(dev)
+    priv = torch.empty(g["priv_bytes"], dtype=torch.uint8, device=dev)
+    pub = torch.empty(g["pub_bytes"] // 2, dtype=torch.int16, device=dev)
+    out = torch.empty(n, dtype=torch.uint8, device=dev)
+    ws = dwtfrag.workspace(n, width, levels, dev)
+
+    def protect():
+        dwtfrag.protect(x, width, levels, key, nonce, priv=priv, pub=pub, ws=ws, launch=launch)
+
+    def restore():
+        dwtfrag.restore(priv, pub, n, width, levels, key, nonce, out=out, ws=ws, launch=launch)
+
+    if args.profile_run:
+        for _ in range(2):
+            out.copy_(x)  # plain copy kernel: reads n bytes, writes n bytes
+        torch.cuda.synchronize()
+        for _ in range(2):
+            protect()
+            restore()
+        torch.cuda.synchronize()
+        log(f"profile run done: n={n} bytes, {n + 2 * H * width} algorithmic bytes per launch")
+        return
+
+    # parity gate: fragments against the oracle's stored digests, restore exact
+    protect()
+    restore()
+    torch.cuda.synchronize()
+    bit_exact = bool(torch.equal(out, x))
+    if not args.no_parity:
+        with open(os.path.join(ROOT, "tests", "golden", "oracle_digests.json")) as f:
+            gold = json.load(f)[args.config]
+        bit_exact &= hashlib.sha256(priv.cpu().numpy().tobytes()).hexdigest() == gold["priv_sha256"]
+        bit_exact &= hashlib.sha256(pub.cpu().numpy().tobytes()).hexdigest() == gold["pub_sha256"]
+    log(f"parity vs oracle: {'bit-exact' if bit_exact else 'MISMATCH'}")
+
+    for _ in range(args.warmup):
+        protect()
+        restore()
+    torch.cuda.synchronize()
+
+    # timed region: K whole steps back to back, events between launches
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        protect()
+        ev[k][1].record(stream)
+        restore()
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    t_prot = [ev[k][0].elapsed_time(ev[k][1]) * 1e3 for k in range(args.steps)]  # us
+    t_rest = [ev[k][1].elapsed_time(ev[k][2]) * 1e3 for k in range(args.steps)]
+    t_pair = [a + b for a, b in zip(t_prot, t_rest)]
+
+    value = n * args.steps / wall / 1e9
+    alg_bytes = n + 2 * H * width  # per launch, each direction
+    avg_p, avg_r = sum(t_prot) / len(t_prot), sum(t_rest) / len(t_rest)
+    dominant = "fwd_kernel" if avg_p >= avg_r else "inv_kernel"
+    dom_us = max(avg_p, avg_r)
+    achieved = alg_bytes / (dom_us * 1e-6) / 1e9
+    traffic = stored_traffic(args.config)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic.get(dominant) if traffic else None,
+                "kernel": dominant, "bytes_per_launch": alg_bytes,
+                "avg_launch_us": round(dom_us, 2)}
+    pair_roof = 2 * alg_bytes / (avg_p + avg_r) / 1e3 / HBM_PEAK_GBS
+
+    cold = None
+    if args.cold:
+        scratch = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        cp, cr = [], []
+        for _ in range(10):
+            scratch.fill_(1)
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record(stream); protect(); e1.record(stream)
+            scratch.fill_(2)
+            e2b = torch.cuda.Event(enable_timing=True)
+            e2b.record(stream); restore(); e2.record(stream)
+            torch.cuda.synchronize()
+            cp.append(e0.elapsed_time(e1) * 1e3)
+            cr.append(e2b.elapsed_time(e2) * 1e3)
+        del scratch
+        cold = {"protect_us_p50": round(percentile(cp, 50), 1),
+                "restore_us_p50": round(percentile(cr, 50), 1),
+                "gbps": round(n / ((percentile(cp, 50) + percentile(cr, 50)) * 1e-6) / 1e9, 1)}
+
+    result = {
+        "metric": "protect+restore GB/s on 1 MI355X (% HBM roofline), bit-exact; p50/p99 latency",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "n_bytes": n, "rows": H, "width": width,
+                   "levels": levels, "launch": {"seg_rows": args.seg_rows, "lane_cols": args.lane_cols}},
+        "bit_exact": bit_exact,
+        "latency_us": {"protect_p50": round(percentile(t_prot, 50), 1),
+                       "protect_p99": round(percentile(t_prot, 99), 1),
+                       "restore_p50": round(percentile(t_rest, 50), 1),
+                       "restore_p99": round(percentile(t_rest, 99), 1),
+                       "pair_p50": round(percentile(t_pair, 50), 1),
+                       "pair_p99": round(percentile(t_pair, 99), 1)},
+        "roofline": roofline,
+        "pair_hbm_frac": round(pair_roof, 4),
+        "cold": cold,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline and args.config == "large":
+        log("timing the CPU oracle on a bounded sample ...")
+        result["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -78,10 +78,16 @@ void expand_key(const uint8_t key[16], const uint8_t nonce[16], AesKey *out);
 
 __device__ __forceinline__ uint32_t bswap32(uint32_t v) { return __builtin_bswap32(v); }
 
+// Key material as staged in LDS: 44 round-key words, then the nonce as
+// (hi low word, hi high word, lo low word, lo high word).
+constexpr int kKeyWords = 48;
+
 // Block j of the counter sequence as 4 little-endian state words.
-__device__ __forceinline__ void counter_block(const AesKey &k, uint64_t j, uint32_t w[4]) {
-  uint64_t lo = k.nonce_lo + j;
-  uint64_t hi = k.nonce_hi + (lo < k.nonce_lo ? 1ull : 0ull);
+__device__ __forceinline__ void counter_block(const uint32_t *kw, uint64_t j, uint32_t w[4]) {
+  const uint64_t nhi = uint64_t(kw[44]) | (uint64_t(kw[45]) << 32);
+  const uint64_t nlo = uint64_t(kw[46]) | (uint64_t(kw[47]) << 32);
+  uint64_t lo = nlo + j;
+  uint64_t hi = nhi + (lo < nlo ? 1ull : 0ull);
   w[0] = bswap32(uint32_t(hi >> 32));
   w[1] = bswap32(uint32_t(hi));
   w[2] = bswap32(uint32_t(lo >> 32));
@@ -89,36 +95,46 @@ __device__ __forceinline__ void counter_block(const AesKey &k, uint64_t j, uint3
 }
 
 // One AES-128 encryption; `te` points at four 256-word tables in LDS
-// (te[256 r + x] = rotl(te0[x], 8 r)).
-__device__ __forceinline__ void aes_encrypt(const uint32_t *te, const AesKey &k, uint32_t w[4]) {
-  uint32_t s0 = w[0] ^ k.rk[0], s1 = w[1] ^ k.rk[1], s2 = w[2] ^ k.rk[2], s3 = w[3] ^ k.rk[3];
+// (te[256 r + x] = rotl(te0[x], 8 r)), `rk` at the 44 round-key words.
+__device__ __forceinline__ void aes_encrypt(const uint32_t *te, const uint32_t *rk, uint32_t w[4]) {
+  uint32_t s0 = w[0] ^ rk[0], s1 = w[1] ^ rk[1], s2 = w[2] ^ rk[2], s3 = w[3] ^ rk[3];
 #define DWTFRAG_TE(r, v) te[256 * (r) + (((v) >> (8 * (r))) & 0xFF)]
 #pragma unroll
   for (int rnd = 1; rnd < 10; ++rnd) {
-    uint32_t t0 = DWTFRAG_TE(0, s0) ^ DWTFRAG_TE(1, s1) ^ DWTFRAG_TE(2, s2) ^ DWTFRAG_TE(3, s3) ^ k.rk[4 * rnd + 0];
-    uint32_t t1 = DWTFRAG_TE(0, s1) ^ DWTFRAG_TE(1, s2) ^ DWTFRAG_TE(2, s3) ^ DWTFRAG_TE(3, s0) ^ k.rk[4 * rnd + 1];
-    uint32_t t2 = DWTFRAG_TE(0, s2) ^ DWTFRAG_TE(1, s3) ^ DWTFRAG_TE(2, s0) ^ DWTFRAG_TE(3, s1) ^ k.rk[4 * rnd + 2];
-    uint32_t t3 = DWTFRAG_TE(0, s3) ^ DWTFRAG_TE(1, s0) ^ DWTFRAG_TE(2, s1) ^ DWTFRAG_TE(3, s2) ^ k.rk[4 * rnd + 3];
+    uint32_t t0 = DWTFRAG_TE(0, s0) ^ DWTFRAG_TE(1, s1) ^ DWTFRAG_TE(2, s2) ^ DWTFRAG_TE(3, s3) ^ rk[4 * rnd + 0];
+    uint32_t t1 = DWTFRAG_TE(0, s1) ^ DWTFRAG_TE(1, s2) ^ DWTFRAG_TE(2, s3) ^ DWTFRAG_TE(3, s0) ^ rk[4 * rnd + 1];
+    uint32_t t2 = DWTFRAG_TE(0, s2) ^ DWTFRAG_TE(1, s3) ^ DWTFRAG_TE(2, s0) ^ DWTFRAG_TE(3, s1) ^ rk[4 * rnd + 2];
+    uint32_t t3 = DWTFRAG_TE(0, s3) ^ DWTFRAG_TE(1, s0) ^ DWTFRAG_TE(2, s1) ^ DWTFRAG_TE(3, s2) ^ rk[4 * rnd + 3];
     s0 = t0; s1 = t1; s2 = t2; s3 = t3;
   }
 #undef DWTFRAG_TE
   // last round: SubBytes + ShiftRows only; S[x] is byte 1 of te0[x]
 #define DWTFRAG_S(v, r) ((te[((v) >> (8 * (r))) & 0xFF] >> 8) & 0xFF)
-  w[0] = (DWTFRAG_S(s0, 0) | (DWTFRAG_S(s1, 1) << 8) | (DWTFRAG_S(s2, 2) << 16) | (DWTFRAG_S(s3, 3) << 24)) ^ k.rk[40];
-  w[1] = (DWTFRAG_S(s1, 0) | (DWTFRAG_S(s2, 1) << 8) | (DWTFRAG_S(s3, 2) << 16) | (DWTFRAG_S(s0, 3) << 24)) ^ k.rk[41];
-  w[2] = (DWTFRAG_S(s2, 0) | (DWTFRAG_S(s3, 1) << 8) | (DWTFRAG_S(s0, 2) << 16) | (DWTFRAG_S(s1, 3) << 24)) ^ k.rk[42];
-  w[3] = (DWTFRAG_S(s3, 0) | (DWTFRAG_S(s0, 1) << 8) | (DWTFRAG_S(s1, 2) << 16) | (DWTFRAG_S(s2, 3) << 24)) ^ k.rk[43];
+  w[0] = (DWTFRAG_S(s0, 0) | (DWTFRAG_S(s1, 1) << 8) | (DWTFRAG_S(s2, 2) << 16) | (DWTFRAG_S(s3, 3) << 24)) ^ rk[40];
+  w[1] = (DWTFRAG_S(s1, 0) | (DWTFRAG_S(s2, 1) << 8) | (DWTFRAG_S(s3, 2) << 16) | (DWTFRAG_S(s0, 3) << 24)) ^ rk[41];
+  w[2] = (DWTFRAG_S(s2, 0) | (DWTFRAG_S(s3, 1) << 8) | (DWTFRAG_S(s0, 2) << 16) | (DWTFRAG_S(s1, 3) << 24)) ^ rk[42];
+  w[3] = (DWTFRAG_S(s3, 0) | (DWTFRAG_S(s0, 1) << 8) | (DWTFRAG_S(s1, 2) << 16) | (DWTFRAG_S(s2, 3) << 24)) ^ rk[43];
 #undef DWTFRAG_S
 }
 
 static __constant__ AesTables c_aes = make_aes_tables();
 
-// Fill the four rotated tables (1024 words) cooperatively; caller syncs.
-__device__ __forceinline__ void load_aes_tables(uint32_t *te) {
+// Fill the four rotated tables (1024 words) and the key words cooperatively;
+// the caller synchronises the block afterwards.
+__device__ __forceinline__ void load_aes_tables(uint32_t *te, uint32_t *kw, const AesKey &key) {
   for (int i = threadIdx.x; i < 1024; i += blockDim.x) {
     const uint32_t v = c_aes.te0[i & 255];
     const int r = 8 * (i >> 8);
     te[i] = r ? ((v << r) | (v >> (32 - r))) : v;
+  }
+  for (int i = threadIdx.x; i < kKeyWords; i += blockDim.x) {
+    uint32_t v;
+    if (i < 44) v = key.rk[i];
+    else if (i == 44) v = uint32_t(key.nonce_hi);
+    else if (i == 45) v = uint32_t(key.nonce_hi >> 32);
+    else if (i == 46) v = uint32_t(key.nonce_lo);
+    else v = uint32_t(key.nonce_lo >> 32);
+    kw[i] = v;
   }
 }
 

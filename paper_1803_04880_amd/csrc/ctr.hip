@@ -9,14 +9,15 @@ __global__ __launch_bounds__(256) void ctr_kernel(const uint8_t *__restrict__ in
                                                   uint8_t *__restrict__ out, uint64_t nbytes,
                                                   const AesKey key, uint64_t first_block) {
   __shared__ uint32_t s_te[1024];
-  load_aes_tables(s_te);
+  __shared__ uint32_t s_kw[kKeyWords];
+  load_aes_tables(s_te, s_kw, key);
   __syncthreads();
   const uint64_t nblk = (nbytes + 15) / 16;
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
   for (uint64_t b = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; b < nblk; b += stride) {
     uint32_t w[4];
-    counter_block(key, first_block + b, w);
-    aes_encrypt(s_te, key, w);
+    counter_block(s_kw, first_block + b, w);
+    aes_encrypt(s_te, s_kw, w);
     const uint64_t off = b * 16;
     const bool vec = off + 16 <= nbytes &&
                      ((reinterpret_cast<uintptr_t>(in + off) | reinterpret_cast<uintptr_t>(out + off)) & 15) == 0;

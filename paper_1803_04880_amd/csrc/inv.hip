@@ -179,7 +179,7 @@ struct InvWave {
       for (int u = 0; u < U; ++u) cur[u] = nxt[u];
       if (k + 1 < kend) load_ll(k + 1, nxt);
       if (P.use_aes) {
-        ks.ensure(k, kend, P.key, lane);
+        ks.ensure(k, kend, lane);
         const int nv = P.wdim[L] - (c0 >> L);
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -196,8 +196,9 @@ __global__ __launch_bounds__(kBlockThreads) void inv_kernel(const int16_t *__res
                                                             void *__restrict__ out,
                                                             const StageParams P) {
   __shared__ uint32_t s_te[1024];
+  __shared__ uint32_t s_kw[kKeyWords];
   __shared__ uint32_t s_ring[kWavesPerBlock][kRingBlocks * 4];
-  if (P.use_aes) load_aes_tables(s_te);
+  if (P.use_aes) load_aes_tables(s_te, s_kw, P.key);
   __syncthreads();
   const int wib = threadIdx.x >> 6;
   const int wave = blockIdx.x * kWavesPerBlock + wib;
@@ -210,6 +211,7 @@ __global__ __launch_bounds__(kBlockThreads) void inv_kernel(const int16_t *__res
   w.lane = threadIdx.x & 63;
   w.ks.ring = s_ring[wib];
   w.ks.te = s_te;
+  w.ks.kw = s_kw;
   w.ks.rows = P.ks_rows;
   w.ks.blocks = P.ks_blocks;
   w.run(wave);

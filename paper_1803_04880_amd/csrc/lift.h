@@ -143,6 +143,7 @@ __device__ __forceinline__ void load_i16(const int16_t *base, int64_t idx, int n
 struct KsRing {
   uint32_t *ring;       // kRingBlocks * 4 words, this wavefront's
   const uint32_t *te;   // AES tables in LDS
+  const uint32_t *kw;   // round keys + nonce in LDS
   int rows, blocks;     // rows per refill, blocks per row slot
   int col_lo, col_hi;   // LL columns needed (clipped to the band)
   int64_t wL;           // LL row length
@@ -152,7 +153,7 @@ struct KsRing {
 
   // Make row k resident; called with the whole wavefront converged, rows in
   // increasing order.  row_end bounds the rows worth computing.
-  __device__ __forceinline__ void ensure(int k, int row_end, const AesKey &key, int lane) {
+  __device__ __forceinline__ void ensure(int k, int row_end, int lane) {
     if (base >= 0 && k >= base && k < base + rows) return;
     base = k;
     if (col_hi > col_lo) {
@@ -164,8 +165,8 @@ struct KsRing {
         const int64_t blast = (2 * (int64_t(r) * wL + col_hi) - 1) >> 4;
         if (b0 + b <= blast) {
           uint32_t w[4];
-          counter_block(key, uint64_t(b0 + b), w);
-          aes_encrypt(te, key, w);
+          counter_block(kw, uint64_t(b0 + b), w);
+          aes_encrypt(te, kw, w);
           uint32_t *dst = ring + idx * 4;
           dst[0] = w[0]; dst[1] = w[1]; dst[2] = w[2]; dst[3] = w[3];
         }
