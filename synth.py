@@ -160,3 +160,14 @@ def batch_buffer(spec) -> np.ndarray:
     if kind == "markov":
         return markov(n, seed)
     return uniform(n, seed)
+
+
+def mlp_init(n_params: int, seed: int) -> np.ndarray:
+    """Seeded float32 starting point of the 8-16-1 context network: the flat
+    vector (W1 16x8, b1 16, W2 16, b2) with W1, W2 ~ N(0, 0.05^2), b1 = 1
+    (hidden units start active) and b2 = 0."""
+    rng = np.random.default_rng(seed)
+    theta = rng.normal(0.0, 0.05, n_params)
+    theta[128:144] = 1.0
+    theta[160] = 0.0
+    return theta.astype(np.float32)
