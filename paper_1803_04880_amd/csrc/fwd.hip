@@ -7,14 +7,18 @@
 // along rows), then the vertical pass, and the next level transforms LL only.
 //
 // One wavefront owns a rectangle of the level-0 grid (a column window times a
-// row segment).  It streams the rows of its window top to bottom, starting
-// halo_t rows above its rectangle and stopping halo_b rows below.  Rows are
-// fetched K at a time into an LDS staging buffer while the previous K rows
-// are being transformed.  Each row is lifted horizontally across the 64 lanes
-// (packed 16-bit arithmetic, see pack.h); the vertical lifting of level l is a
-// per-column state machine in registers that consumes the level's rows as they
-// are produced and emits one low row and one high row per row pair.  Low rows
-// feed level l+1; everything inside the owned rectangle is stored.
+// row segment) and streams the rows of its window top to bottom, starting
+// halo_t rows above its rectangle and stopping halo_b rows below.  Work goes
+// in batches of K level-0 rows: the batch sits in an LDS staging buffer (the
+// next batch's vector loads are in flight meanwhile) and is pushed through the
+// levels one after the other.  Level l takes its rows from an LDS queue,
+// lifts each row horizontally across the 64 lanes (packed 16-bit arithmetic,
+// see pack.h) and runs the vertical lifting as a per-column state machine in
+// registers: an odd row waits, the following even row completes the pair
+// (2k+1, 2k+2), which yields low row k and high row k.  Low rows go to level
+// l+1's queue (or, at the last level, to the LL output), detail rows inside the
+// owned rectangle are stored.  Rows a level cannot pair yet stay in registers
+// until the next batch.
 #include "lift.h"
 #include "pack.h"
 
@@ -24,40 +28,59 @@ template <int L, int C1, bool U8IN>
 struct FwdWave {
   template <int l> static constexpr int M = (C1 >> (l - 1)) / 2;  // evens per lane at level l
   template <int l> static constexpr int NP = Pk<M<l>>::P;         // packed regs per parity
+  template <int l> static constexpr int R = 2 * NP<l>;            // packed regs per row
   static constexpr int RB = U8IN ? C1 : 2 * C1;                   // input bytes per lane and row
   static constexpr int RW = RB / 4;                               // ... in dwords
-  static constexpr int K = (4096 / (64 * RB)) >= 2 ? 4096 / (64 * RB) : 2;  // rows per batch
+  static constexpr int K = 8;                                     // level-0 rows per batch
+  // queue capacity (rows) of level l >= 2: rows level l-1 can emit in one batch
+  template <int l> static constexpr int QC = (K >> (l - 1)) + 2;
+  static constexpr int kStageWords = K * 64 * RW;
+  static constexpr int kQueueWords = 64 * (QC<2> * R<2> + (L >= 3 ? QC<3> * R<3> : 0) +
+                                           (L >= 4 ? QC<4> * R<4> : 0));
+  static constexpr int kLdsWords = kStageWords + kQueueWords;
 
   const StageParams &G;
   const uint8_t *in8;
   const int16_t *in16;
   int16_t *pub;
   int16_t *llout;
-  uint32_t *stage;        // this wavefront's LDS staging rows: K * 64 * RW dwords
+  uint32_t *lds;          // this wavefront's staging rows, then the level queues
   int lane;
   int c0;                 // level-0 column of this lane's first sample
   int X0, Y0, X1, Y1;     // owned rectangle (level 0), X1 / Y1 exclusive
   bool last_win, last_seg;
+  int r0;                 // first level-0 row streamed (level l starts at r0 >> (l-1))
 
-  uint32_t Ev1[2 * NP<1>], Ov1[2 * NP<1>], Dv1[2 * NP<1>];
-  uint32_t Ev2[2 * NP<2>], Ov2[2 * NP<2>], Dv2[2 * NP<2>];
-  uint32_t Ev3[L >= 3 ? 2 * NP<3> : 1], Ov3[L >= 3 ? 2 * NP<3> : 1], Dv3[L >= 3 ? 2 * NP<3> : 1];
-  uint32_t Ev4[L >= 4 ? 2 * NP<4> : 1], Ov4[L >= 4 ? 2 * NP<4> : 1], Dv4[L >= 4 ? 2 * NP<4> : 1];
-  int i0[kMaxFused + 1];  // first row of each level's stream
+  // per-level registers: previous even row, previous high row, waiting odd row
+  uint32_t E1[R<1>], D1[R<1>], P1[R<1>];
+  uint32_t E2[R<2>], D2[R<2>], P2[R<2>];
+  uint32_t E3[L >= 3 ? R<3> : 1], D3[L >= 3 ? R<3> : 1], P3[L >= 3 ? R<3> : 1];
+  uint32_t E4[L >= 4 ? R<4> : 1], D4[L >= 4 ? R<4> : 1], P4[L >= 4 ? R<4> : 1];
+  int icnt[kMaxFused + 1];  // next row index of each level's stream
+  int qn[kMaxFused + 1];    // rows waiting in each level's queue this batch
   bool hedge[kMaxFused + 1];
   bool lown[kMaxFused + 1];
 
   template <int l> __device__ __forceinline__ auto &E() {
-    if constexpr (l == 1) return Ev1; else if constexpr (l == 2) return Ev2;
-    else if constexpr (l == 3) return Ev3; else return Ev4;
-  }
-  template <int l> __device__ __forceinline__ auto &O() {
-    if constexpr (l == 1) return Ov1; else if constexpr (l == 2) return Ov2;
-    else if constexpr (l == 3) return Ov3; else return Ov4;
+    if constexpr (l == 1) return E1; else if constexpr (l == 2) return E2;
+    else if constexpr (l == 3) return E3; else return E4;
   }
   template <int l> __device__ __forceinline__ auto &D() {
-    if constexpr (l == 1) return Dv1; else if constexpr (l == 2) return Dv2;
-    else if constexpr (l == 3) return Dv3; else return Dv4;
+    if constexpr (l == 1) return D1; else if constexpr (l == 2) return D2;
+    else if constexpr (l == 3) return D3; else return D4;
+  }
+  template <int l> __device__ __forceinline__ auto &Pw() {
+    if constexpr (l == 1) return P1; else if constexpr (l == 2) return P2;
+    else if constexpr (l == 3) return P3; else return P4;
+  }
+
+  // LDS queue of level l >= 2: QC<l> rows of R<l> words per lane, after the
+  // staging rows and the queues of the finer levels.
+  template <int l> __device__ __forceinline__ uint32_t *queue() const {
+    int off = kStageWords;
+    if constexpr (l >= 3) off += 64 * QC<2> * R<2>;
+    if constexpr (l >= 4) off += 64 * QC<3> * R<3>;
+    return lds + off;
   }
 
   template <int l> __device__ __forceinline__ bool row_owned(int k) const {
@@ -66,24 +89,25 @@ struct FwdWave {
 
   // Store Mv int16 values (packed pairs) at band columns bc.. of a band row.
   template <int Mv>
-  __device__ __forceinline__ void store_band(int16_t *row, int bc, int nvalid, const uint32_t *R) {
+  __device__ __forceinline__ void store_band(int16_t *row, int bc, int nvalid, const uint32_t *V) {
     if (nvalid <= 0) return;
     int16_t *dst = reinterpret_cast<int16_t *>(reinterpret_cast<char *>(row) + 2u * uint32_t(bc));
     const bool aligned = (reinterpret_cast<uintptr_t>(row) & (2 * Mv - 1)) == 0;
     if (nvalid >= Mv && aligned) {
-      if constexpr (Mv == 1) *dst = int16_t(R[0]);
-      else if constexpr (Mv == 2) *reinterpret_cast<uint32_t *>(dst) = R[0];
-      else if constexpr (Mv == 4) *reinterpret_cast<uint2 *>(dst) = make_uint2(R[0], R[1]);
-      else *reinterpret_cast<uint4 *>(dst) = make_uint4(R[0], R[1], R[2], R[3]);
+      if constexpr (Mv == 1) *dst = int16_t(V[0]);
+      else if constexpr (Mv == 2) *reinterpret_cast<uint32_t *>(dst) = V[0];
+      else if constexpr (Mv == 4) *reinterpret_cast<uint2 *>(dst) = make_uint2(V[0], V[1]);
+      else *reinterpret_cast<uint4 *>(dst) = make_uint4(V[0], V[1], V[2], V[3]);
       return;
     }
 #pragma unroll
     for (int u = 0; u < Mv; ++u)
-      if (u < nvalid) dst[u] = int16_t(Mv == 1 ? R[0] : (R[u >> 1] >> (16 * (u & 1))));
+      if (u < nvalid) dst[u] = int16_t(Mv == 1 ? V[0] : (V[u >> 1] >> (16 * (u & 1))));
   }
 
-  // Low row k of level l: lows -> LL_l (next level / private fragment), highs -> HL_l.
-  template <int l> __device__ __forceinline__ void emit_low(const uint32_t (&s)[2 * NP<l>], int k) {
+  // Low row k of level l: lows -> LL_l (next level's queue / LL output),
+  // highs -> HL_l.
+  template <int l> __device__ __forceinline__ void emit_low(const uint32_t (&s)[R<l>], int k) {
     constexpr int Np = NP<l>;
     const int N = G.wdim[l - 1];
     const int wl = G.wdim[l];
@@ -94,25 +118,28 @@ struct FwdWave {
     if constexpr (l < L) {
       constexpr int Mn = M<l + 1>;
       constexpr int Nn = NP<l + 1>;
-      uint32_t E2[Nn], O2[Nn];
+      uint32_t *dst = queue<l + 1>() + (qn[l + 1] * 64 + lane) * R<l + 1>;
+      uint32_t e[Nn], o[Nn];
       if constexpr (Mn >= 2) {
 #pragma unroll
         for (int j = 0; j < Nn; ++j) {
-          E2[j] = lo_halves(s[2 * j], s[2 * j + 1]);
-          O2[j] = hi_halves(s[2 * j], s[2 * j + 1]);
+          e[j] = lo_halves(s[2 * j], s[2 * j + 1]);
+          o[j] = hi_halves(s[2 * j], s[2 * j + 1]);
         }
       } else {
-        E2[0] = s[0];
-        O2[0] = s[0] >> 16;
+        e[0] = s[0];
+        o[0] = s[0] >> 16;
       }
-      push_row<l + 1>(E2, O2, k);
+#pragma unroll
+      for (int j = 0; j < Nn; ++j) { dst[j] = e[j]; dst[Nn + j] = o[j]; }
+      qn[l + 1] += 1;
     } else {
       if (rown && lown[l]) store_band<M<l>>(llout + int64_t(k) * wl, bc, wl - bc, s);
     }
   }
 
   // High row k of level l: lows -> LH_l, highs -> HH_l.
-  template <int l> __device__ __forceinline__ void emit_high(const uint32_t (&d)[2 * NP<l>], int k) {
+  template <int l> __device__ __forceinline__ void emit_high(const uint32_t (&d)[R<l>], int k) {
     if (!(row_owned<l>(k) && lown[l])) return;
     constexpr int Np = NP<l>;
     const int N = G.wdim[l - 1];
@@ -122,71 +149,89 @@ struct FwdWave {
     store_band<M<l>>(pub + G.off_hh[l] + int64_t(k) * (N - wl), bc, (N - wl) - bc, d + Np);
   }
 
-  // Row i of the level-(l-1) LL arrives at level l in even/odd packed form.
-  // While streaming, a row yields at most one low and one high row: the even
-  // rows complete the pair (i-2, i-1), the last row of an even-length signal
-  // completes the final pair.  The extra low row of an odd-length signal is
-  // produced by flush_tail once the stream has ended.
-  template <int l>
-  __device__ __forceinline__ void push_row(uint32_t (&Ein)[NP<l>], uint32_t (&Oin)[NP<l>], int i) {
-    constexpr int Np = NP<l>;
-    constexpr int R = 2 * Np;
-    hfwd_pk_any<M<l>>(Ein, Oin, c0 >> (l - 1), G.wdim[l - 1], hedge[l]);
-    uint32_t x[R];
-#pragma unroll
-    for (int j = 0; j < Np; ++j) { x[j] = Ein[j]; x[Np + j] = Oin[j]; }
+  // Row i of level l, already lifted horizontally (x = lows | highs).
+  template <int l> __device__ __forceinline__ void vertical(const uint32_t (&x)[R<l>], int i) {
+    constexpr int Rl = R<l>;
     const int N = G.hdim[l - 1];
+    auto &Ev = E<l>();
+    auto &Dv = D<l>();
+    auto &Pv = Pw<l>();
     if (N == 1) {  // no vertical pass: the row is the low row
       emit_low<l>(x, 0);
       return;
     }
-    auto &Ev = E<l>();
-    auto &Ov = O<l>();
-    auto &Dv = D<l>();
-    const bool even = (i & 1) == 0;
-    if (even && i == i0[l]) {
+    if (i == (r0 >> (l - 1))) {  // first row of this stream (even)
 #pragma unroll
-      for (int t = 0; t < R; ++t) Ev[t] = x[t];
+      for (int t = 0; t < Rl; ++t) Ev[t] = x[t];
       return;
     }
-    if (!even && i != N - 1) {
+    const bool odd = (i & 1) != 0;
+    if (odd && i != N - 1) {  // waits for its even partner
 #pragma unroll
-      for (int t = 0; t < R; ++t) Ov[t] = x[t];
+      for (int t = 0; t < Rl; ++t) Pv[t] = x[t];
       return;
     }
-    // even i: rows i-2 (Ev), i-1 (Ov), i (x) give d(i-1), s(i-2);
-    // odd i = N-1: rows i-1 (Ev), i (x) with x(N) = x(N-2) give d(i), s(i-1)
-    const int k = even ? (i - 2) >> 1 : (i - 1) >> 1;
+    // pair (2k+1, 2k+2): odd row o, even row e; at the end of an even-length
+    // signal the odd row is x itself and x(N) = x(N-2), the previous even row
+    const int k = odd ? (i - 1) >> 1 : (i - 2) >> 1;
     const bool top = (k == 0);
-    uint32_t low[R], high[R];
+    uint32_t low[Rl], high[Rl];
 #pragma unroll
-    for (int t = 0; t < R; ++t) {
-      const uint32_t dn = even ? pk_predict(Ov[t], Ev[t], x[t]) : pk_sub(x[t], Ev[t]);
+    for (int t = 0; t < Rl; ++t) {
+      const uint32_t o = odd ? x[t] : Pv[t];
+      const uint32_t e = odd ? Ev[t] : x[t];
+      const uint32_t dn = pk_predict(o, Ev[t], e);
       low[t] = pk_update(Ev[t], top ? dn : Dv[t], dn);
       high[t] = dn;
       Dv[t] = dn;
-      if (even) Ev[t] = x[t];
+      Ev[t] = e;
     }
     emit_high<l>(high, k);
     emit_low<l>(low, k);
-  }
-
-  // End of the stream at the bottom edge: odd-length levels still owe their
-  // last low row s(N-1) = x(N-1) + floor((d(N-2) + d(N) + 2) / 4), d(N) = d(N-2).
-  // Levels are flushed in order, so a flushed row reaches the coarser levels
-  // before they flush themselves.
-  template <int l> __device__ __forceinline__ void flush_tail() {
-    const int N = G.hdim[l - 1];
-    if (N > 1 && (N & 1)) {
-      constexpr int R = 2 * NP<l>;
-      auto &Ev = E<l>();
-      auto &Dv = D<l>();
-      uint32_t low[R];
+    if (!odd && i == N - 1) {  // odd length: s(N-1) with d(N) = d(N-2)
 #pragma unroll
-      for (int t = 0; t < R; ++t) low[t] = pk_update(Ev[t], Dv[t], Dv[t]);
+      for (int t = 0; t < Rl; ++t) low[t] = pk_update(Ev[t], Dv[t], Dv[t]);
       emit_low<l>(low, (N - 1) >> 1);
     }
-    if constexpr (l < L) flush_tail<l + 1>();
+  }
+
+  // ---- level phases ------------------------------------------------------
+  // Level 1 consumes nb staged rows starting at level-0 row rb.
+  __device__ __forceinline__ void phase1(int rb, int nb, bool staged) {
+#pragma unroll 1
+    for (int r = 0; r < nb; ++r) {
+      uint32_t w[RW], Ein[NP<1>], Oin[NP<1>];
+      if (staged) stage_read(r, w);
+      else load_row_slow(rb + r, w);
+      unpack(w, Ein, Oin);
+      hfwd_pk_any<M<1>>(Ein, Oin, c0, G.wdim[0], hedge[1]);
+      uint32_t x[R<1>];
+#pragma unroll
+      for (int j = 0; j < NP<1>; ++j) { x[j] = Ein[j]; x[NP<1> + j] = Oin[j]; }
+      vertical<1>(x, icnt[1]);
+      icnt[1] += 1;
+    }
+  }
+
+  // Level l >= 2 consumes the rows level l-1 queued in this batch.
+  template <int l> __device__ __forceinline__ void phase() {
+    constexpr int Np = NP<l>;
+    const int n = qn[l];
+    qn[l] = 0;
+    const uint32_t *q = queue<l>();
+#pragma unroll 1
+    for (int r = 0; r < n; ++r) {
+      const uint32_t *src = q + (r * 64 + lane) * R<l>;
+      uint32_t Ein[Np], Oin[Np];
+#pragma unroll
+      for (int j = 0; j < Np; ++j) { Ein[j] = src[j]; Oin[j] = src[Np + j]; }
+      hfwd_pk_any<M<l>>(Ein, Oin, c0 >> (l - 1), G.wdim[l - 1], hedge[l]);
+      uint32_t x[R<l>];
+#pragma unroll
+      for (int j = 0; j < Np; ++j) { x[j] = Ein[j]; x[Np + j] = Oin[j]; }
+      vertical<l>(x, icnt[l]);
+      icnt[l] += 1;
+    }
   }
 
   // ---- input rows --------------------------------------------------------
@@ -249,7 +294,7 @@ struct FwdWave {
   }
 
   __device__ __forceinline__ void stage_write(int k, const uint32_t (&w)[RW]) {
-    uint32_t *dst = stage + (k * 64 + lane) * RW;
+    uint32_t *dst = lds + (k * 64 + lane) * RW;
     if constexpr (RW == 2) {
       *reinterpret_cast<uint2 *>(dst) = make_uint2(w[0], w[1]);
     } else {
@@ -259,7 +304,7 @@ struct FwdWave {
     }
   }
   __device__ __forceinline__ void stage_read(int k, uint32_t (&w)[RW]) const {
-    const uint32_t *src = stage + (k * 64 + lane) * RW;
+    const uint32_t *src = lds + (k * 64 + lane) * RW;
     if constexpr (RW == 2) {
       const uint2 v = *reinterpret_cast<const uint2 *>(src);
       w[0] = v.x; w[1] = v.y;
@@ -283,35 +328,31 @@ struct FwdWave {
     Y1 = last_seg ? G.H : Y0 + G.own_h;
     const int cbase = (win == 0) ? 0 : X0 - G.halo_l;
     c0 = cbase + lane * C1;
-    const int r0 = Y0 > G.halo_t ? Y0 - G.halo_t : 0;
+    r0 = Y0 > G.halo_t ? Y0 - G.halo_t : 0;
     const int r1 = min(G.H, Y1 + G.halo_b);
 #pragma unroll
     for (int l = 1; l <= L; ++l) {
-      i0[l] = r0 >> (l - 1);
       const int N = G.wdim[l - 1];
       const int j0 = cbase >> (l - 1);
       const int span = (64 * C1) >> (l - 1);
       hedge[l] = (j0 == 0) || (N - 1 >= j0 && N - 1 < j0 + span);
       const int bc = c0 >> l;
       lown[l] = bc >= (X0 >> l) && (last_win || bc < (X1 >> l));
+      icnt[l] = r0 >> (l - 1);
+      qn[l] = 0;
     }
 #pragma unroll
-    for (int t = 0; t < 2 * NP<1>; ++t) { Ev1[t] = 0; Ov1[t] = 0; Dv1[t] = 0; }
+    for (int t = 0; t < R<1>; ++t) { E1[t] = 0; D1[t] = 0; P1[t] = 0; }
 #pragma unroll
-    for (int t = 0; t < 2 * NP<2>; ++t) { Ev2[t] = 0; Ov2[t] = 0; Dv2[t] = 0; }
+    for (int t = 0; t < R<2>; ++t) { E2[t] = 0; D2[t] = 0; P2[t] = 0; }
 #pragma unroll
-    for (int t = 0; t < (L >= 3 ? 2 * NP<3> : 1); ++t) { Ev3[t] = 0; Ov3[t] = 0; Dv3[t] = 0; }
+    for (int t = 0; t < (L >= 3 ? R<3> : 1); ++t) { E3[t] = 0; D3[t] = 0; P3[t] = 0; }
 #pragma unroll
-    for (int t = 0; t < (L >= 4 ? 2 * NP<4> : 1); ++t) { Ev4[t] = 0; Ov4[t] = 0; Dv4[t] = 0; }
+    for (int t = 0; t < (L >= 4 ? R<4> : 1); ++t) { E4[t] = 0; D4[t] = 0; P4[t] = 0; }
     if (r0 >= r1) return;
 
-    // Batches of K rows: while batch b is transformed from the LDS staging
-    // buffer, the vector loads of batch b+1 are in flight in registers.  Rows
-    // that cannot be loaded as one vector per lane are read element-wise
-    // when they are transformed.
     uint32_t q[K][RW];
-    const int cbase_ = cbase;
-    bool fast_cur = row_fast(min(r1, r0 + K) - 1, cbase_);
+    bool fast_cur = row_fast(min(r1, r0 + K) - 1, cbase);
     if (fast_cur) {
 #pragma unroll
       for (int k = 0; k < K; ++k)
@@ -324,22 +365,18 @@ struct FwdWave {
     for (int rb = r0; rb < r1; rb += K) {
       const int nb = min(K, r1 - rb);
       const int rn = rb + K;
-      const bool fast_next = rn < r1 && row_fast(min(r1, rn + K) - 1, cbase_);
+      const bool fast_next = rn < r1 && row_fast(min(r1, rn + K) - 1, cbase);
       if (fast_next) {
 #pragma unroll
         for (int k = 0; k < K; ++k)
           if (rn + k < r1) load_row_fast(rn + k, q[k]);  // next batch in flight
       }
-#pragma unroll 1
-      for (int k = 0; k < nb; ++k) {
-        uint32_t w[RW], Ein[NP<1>], Oin[NP<1>];
-        if (fast_cur) stage_read(k, w);
-        else load_row_slow(rb + k, w);
-        unpack(w, Ein, Oin);
-        push_row<1>(Ein, Oin, rb + k);
-      }
+      phase1(rb, nb, fast_cur);
+      wave_lds_sync();
+      if constexpr (L >= 2) { phase<2>(); wave_lds_sync(); }
+      if constexpr (L >= 3) { phase<3>(); wave_lds_sync(); }
+      if constexpr (L >= 4) { phase<4>(); wave_lds_sync(); }
       if (fast_next) {
-        wave_lds_sync();
 #pragma unroll
         for (int k = 0; k < K; ++k)
           if (rn + k < r1) stage_write(k, q[k]);
@@ -347,7 +384,6 @@ struct FwdWave {
       }
       fast_cur = fast_next;
     }
-    if (r1 == G.H) flush_tail<1>();
   }
 };
 
@@ -357,8 +393,10 @@ __global__ __launch_bounds__(kBlockThreads) void fwd_kernel(const void *__restri
                                                             int16_t *__restrict__ llout,
                                                             const StageParams P) {
   using W = FwdWave<L, C1, U8IN>;
-  __shared__ uint32_t s_stage[kWavesPerBlock][W::K * 64 * W::RW];
-  const int wib = threadIdx.x >> 6;
+  __shared__ uint32_t s_lds[kWavesPerBlock][W::kLdsWords];
+  // the wavefront index is uniform; readfirstlane lets the compiler see that,
+  // so all row / level bookkeeping derived from it stays scalar
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wave = blockIdx.x * kWavesPerBlock + wib;
   if (wave >= P.n_waves) return;
   W w{P};
@@ -366,7 +404,7 @@ __global__ __launch_bounds__(kBlockThreads) void fwd_kernel(const void *__restri
   w.in16 = static_cast<const int16_t *>(in);
   w.pub = pub;
   w.llout = llout;
-  w.stage = s_stage[wib];
+  w.lds = s_lds[wib];
   w.lane = threadIdx.x & 63;
   w.run(wave);
 }

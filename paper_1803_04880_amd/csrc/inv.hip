@@ -200,7 +200,9 @@ __global__ __launch_bounds__(kBlockThreads) void inv_kernel(const int16_t *__res
   __shared__ uint32_t s_ring[kWavesPerBlock][kRingBlocks * 4];
   if (P.use_aes) load_aes_tables(s_te, s_kw, P.key);
   __syncthreads();
-  const int wib = threadIdx.x >> 6;
+  // the wavefront index is uniform; readfirstlane lets the compiler see that,
+  // so all row / level bookkeeping derived from it stays scalar
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wave = blockIdx.x * kWavesPerBlock + wib;
   if (wave >= P.n_waves) return;
   InvWave<L, C1, U8OUT> w{P};

@@ -64,7 +64,12 @@ template <int M, bool EDGE>
 __device__ __forceinline__ void hfwd_pk(uint32_t (&E)[Pk<M>::P], uint32_t (&O)[Pk<M>::P], int j0, int N) {
   constexpr int P = Pk<M>::P;
   const uint32_t nxt = uint32_t(from_next_lane(int(E[0])));
-  const int tgt = N - 1 - j0;
+  int tgt = N - 1 - j0;
+  if (EDGE) {
+    // recompute the edge masks at every use rather than keeping them live in
+    // registers for the whole stream (only edge wavefronts run this)
+    asm volatile("" : "+v"(tgt), "+v"(j0));
+  }
   uint32_t D[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
