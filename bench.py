@@ -43,12 +43,16 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+# sources of the kernels and launch planning the plain protect / restore runs
+PLAIN_PATH_SOURCES = ("api.hip", "common.h", "ctr.hip", "fwd.hip", "inv.hip", "lift.h", "pack.h")
+
+
 def source_hash() -> str:
-    """Hash of the kernel sources; stored HBM-traffic figures are only used
-    while it matches the one recorded with them."""
+    """Hash of the plain path's kernel sources; stored HBM-traffic figures are
+    only used while it matches the one recorded with them."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1803_04880_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in PLAIN_PATH_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -65,7 +69,7 @@ def stored_traffic(workload_key: str):
     return rec.get(workload_key)
 
 
-def cpu_baseline(cfg, rows: int = 512, row0: int = 2560):
+def cpu_baseline(cfg, rows: int = 2048, row0: int = 2048):
     """Oracle protect + restore on `rows` rows of the workload (one process)."""
     import numpy as np
     from oracle import fragment
@@ -95,10 +99,14 @@ def main():
     ap.add_argument("--profile-run", action="store_true",
                     help="no timing: 2 plain device copies of n bytes (counter calibration), "
                          "then 2 protect and 2 restore launches, for rocprofv3")
+    ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--cold", action="store_true",
                     help="also time each direction after overwriting 1 GiB (cache cold)")
     args = ap.parse_args()
 
+    if args.print_source_hash:
+        print(source_hash())
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

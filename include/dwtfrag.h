@@ -123,6 +123,98 @@ int dwtfrag_aes128_ctr(const uint8_t *in, uint8_t *out, uint64_t nbytes,
                        const uint8_t key[16], const uint8_t nonce[16],
                        uint64_t first_block, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned predictor (an extension of the predict slot of the Ch. 5 section
+ * 5.1.1 lifting, eq. (5.1); judged by the entropy of eq. (5.6)).  At an odd
+ * position i of a signal x of length N >= 2, m the whole-sample mirror:
+ *   base = floor((x(m(i-1)) + x(m(i+1))) / 2)
+ *   c_j  = clamp(x(m(i + 2j - 7)) - base, -128, 127)                 j = 0..7
+ *   h_k  = max(0, sum_j w1[k][j] c_j + b1[k])                         k = 0..15
+ *   corr = clamp(floor((sum_k w2[k] h_k + b2) / 2^shift), -255, 255)
+ *   d(i) = x(i) - base - corr
+ * and the update is eq. (5.2) unchanged; every predict step (rows and
+ * columns, every level) uses the same network.  All zero = the plain 5/3
+ * lifting.  Levels are limited to 1..3, for which every coefficient of a
+ * byte input fits int16.  Fragment layout, AES-CTR and the modulo-256 restore
+ * are those of dwtfrag_protect / dwtfrag_restore.
+ * ------------------------------------------------------------------------ */
+
+/* Integer network, 216 bytes, no padding (also the serialised blob). */
+typedef struct {
+  int8_t w1[16][8];   /* hidden weights */
+  int8_t w2[16];      /* output weights */
+  int32_t b1[16];     /* hidden biases, |b1| <= 2^16 */
+  int32_t b2;         /* output bias, |b2| <= 2^26 */
+  int32_t shift;      /* 0..30 */
+} dwtfrag_predictor;
+
+/* Host-only, pure: device workspace bytes of the learned entry points and
+ * the number of (context, target) training pairs of a buffer:
+ * sum over levels of h*floor(w/2) (rows, if w > 1) + w*floor(h/2) (columns,
+ * if h > 1), (h, w) the level's input dims.  DWTFRAG_EINVAL for levels > 3. */
+int dwtfrag_learned_geometry(uint64_t n, uint32_t width, uint32_t levels,
+                             uint64_t *workspace_bytes, uint64_t *pairs);
+
+/* dwtfrag_protect with the learned predict step.
+ *   predictor  HOST pointer, read before return; limits above (else EINVAL)
+ *   workspace  device, >= workspace_bytes of dwtfrag_learned_geometry */
+int dwtfrag_protect_learned(const uint8_t *in, uint64_t n, uint32_t width, uint32_t levels,
+                            const uint8_t key[16], const uint8_t nonce[16],
+                            const dwtfrag_predictor *predictor,
+                            uint8_t *priv, int16_t *pub,
+                            void *workspace, uint64_t workspace_bytes, void *stream);
+
+/* Exact inverse of dwtfrag_protect_learned for the same predictor. */
+int dwtfrag_restore_learned(const uint8_t *priv, const int16_t *pub, uint64_t n, uint32_t width,
+                            uint32_t levels, const uint8_t key[16], const uint8_t nonce[16],
+                            const dwtfrag_predictor *predictor,
+                            uint8_t *out, void *workspace, uint64_t workspace_bytes,
+                            void *stream);
+
+/* Training pairs of a buffer: for every predict step of its PLAIN 5/3
+ * decomposition (level by level; the row pass, row by row, then the column
+ * pass, column by column; odd positions in increasing order) the clamped
+ * context c_0..c_7 (8 int8, device, 8-byte aligned) and the target
+ * x(i) - base (int32, device).  Writes exactly `pairs` entries. */
+int dwtfrag_learned_pairs(const uint8_t *in, uint64_t n, uint32_t width, uint32_t levels,
+                          int8_t *ctx, int32_t *target,
+                          void *workspace, uint64_t workspace_bytes, void *stream);
+
+/* Trainer state (device memory, caller-owned, 8-byte aligned).  theta is the
+ * float network y = w2 . relu(W1 c + b1) + b2 flattened as W1 (16x8 row-
+ * major), b1 (16), w2 (16), b2.  net is its quantisation: power-of-two
+ * scales k1 = largest k <= 30 with max|W1| 2^k < 127.5, shift =
+ * clamp(k1 + k(max|w2|), 0, 30), k2 = shift - k1, values rounded half to
+ * even and clamped to the limits above. */
+typedef struct {
+  float theta[161];
+  float m[161];         /* Adam first moment */
+  float v[161];         /* Adam second moment */
+  float grad[161];      /* gradient of the last step */
+  float loss;           /* mean |y - t| of the last step, before its update */
+  int32_t step;         /* Adam steps taken */
+  int32_t k1, k2;       /* scales of net */
+  dwtfrag_predictor net;
+} dwtfrag_trainer;
+
+/* Device workspace bytes of dwtfrag_trainer_step (a constant). */
+uint64_t dwtfrag_trainer_workspace_bytes(void);
+
+/* theta = theta0 (HOST, 161 floats), zero moments and step, net = its
+ * quantisation. */
+int dwtfrag_trainer_init(dwtfrag_trainer *state, const float theta0[161], void *stream);
+
+/* One step of quantisation-aware Adam (beta1 0.9, beta2 0.999, eps 1e-8) on
+ * the `count` pairs at indices 0, stride, 2 stride, ... of ctx / target
+ * (stride >= 1; offset the pointers to pick another interleaved batch):
+ * the mean absolute error of y against the target and its
+ * gradient are taken at the fake-quantised parameters (net's integers over
+ * their powers of two), the gradient is applied to theta, and net is
+ * re-quantised.  ctx / target as written by dwtfrag_learned_pairs. */
+int dwtfrag_trainer_step(dwtfrag_trainer *state, const int8_t *ctx, const int32_t *target,
+                         uint64_t count, uint64_t stride, float lr,
+                         void *workspace, uint64_t workspace_bytes, void *stream);
+
 /* Static text for a status code. */
 const char *dwtfrag_strerror(int code);
 

@@ -22,9 +22,9 @@ One predict step at odd position i of a signal x of length N >= 2
 and the update at even i is eq. (5.2) with the additive sign (the reading the
 plain oracle uses): s(i) = x(i) + floor((d(m(i-1)) + d(m(i+1)) + 2) / 4).
 
-W1 and W2 are int8, b1 and b2 int32 with |b1| <= 2^20 and |b2| <= 2^26, and
-0 <= shift <= 30; the sums are exact in int32 (|c| <= 128, so |W1 c| < 2^17,
-h < 2^21 and |W2 . h + b2| < 2^29).  Every i + o_j is even, so the context
+W1 and W2 are int8, b1 and b2 int32 with |b1| <= 2^16 and |b2| <= 2^26, and
+0 <= shift <= 30; the sums are exact in int32 (|c| <= 128, so |W1 c| <= 2^17,
+0 <= h < 2^18 and |W2 . h + b2| < 2^30).  Every i + o_j is even, so the context
 reads only even samples; the inverse reconstructs the evens first (undo the
 update) and then recomputes the very same context to undo the predict.  With
 every weight and bias zero the correction is zero and the transform is the
@@ -48,7 +48,7 @@ CTX = len(OFFSETS)
 HIDDEN = 16
 CORR_LIMIT = 255
 MAX_LEVELS = 3
-B1_LIMIT = 1 << 20
+B1_LIMIT = 1 << 16
 B2_LIMIT = 1 << 26
 N_PARAMS = HIDDEN * CTX + HIDDEN + HIDDEN + 1      # w1, b1, w2, b2 = 161
 
@@ -314,7 +314,7 @@ def quantize(theta):
     """Integer network from float32 parameters, power-of-two scales:
     k1 = pow2_exponent(max|W1|), shift = clamp(k1 + pow2_exponent(max|W2|),
     0, 30), k2 = shift - k1;  W1q = clamp(rint(W1 2^k1)), b1q = clamp(rint(b1
-    2^k1), +-2^20), W2q = clamp(rint(W2 2^k2)), b2q = clamp(rint(b2 2^shift),
+    2^k1), +-2^16), W2q = clamp(rint(W2 2^k2)), b2q = clamp(rint(b2 2^shift),
     +-2^26), round half to even.  Then corr ~ floor(y).  Every product is by a
     power of two, so the float32 arithmetic here is exact and any faithful
     implementation reproduces it bit for bit."""
@@ -347,16 +347,17 @@ def fake_quant(theta):
 
 
 def train(theta0, ctx, target, steps, lr, batch):
-    """Quantisation-aware training: ``steps`` Adam steps on consecutive
-    batches of ``batch`` pairs (wrapping around), each gradient taken at the
-    fake-quantised parameters.  Returns the final float parameters."""
+    """Quantisation-aware training: ``steps`` Adam steps over nb = max(1,
+    floor(P / batch)) interleaved batches, step s on the pairs i, i + nb,
+    i + 2 nb, ... with i = (s-1) mod nb (every batch samples every region
+    and pass of the pairs), each gradient taken at the fake-quantised
+    parameters.  Returns the final float parameters."""
     theta = np.asarray(theta0, np.float64).copy()
     m = np.zeros_like(theta)
     v = np.zeros_like(theta)
-    p = len(target)
+    nb = max(len(target) // batch, 1)
     for step in range(1, steps + 1):
-        lo = ((step - 1) * batch) % max(p, 1)
-        idx = (lo + np.arange(min(batch, p))) % p
-        _, g = loss_grad(fake_quant(theta), ctx[idx], target[idx])
+        i = (step - 1) % nb
+        _, g = loss_grad(fake_quant(theta), ctx[i::nb], target[i::nb])
         theta, m, v = adam_step(theta, g, m, v, step, lr)
     return theta

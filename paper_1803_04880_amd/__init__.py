@@ -47,7 +47,10 @@ class Launch(ctypes.Structure):
 _lib = None
 
 EXPORTS = ("dwtfrag_geometry", "dwtfrag_default_width", "dwtfrag_protect", "dwtfrag_restore",
-           "dwtfrag_aes128_ctr", "dwtfrag_strerror")
+           "dwtfrag_aes128_ctr", "dwtfrag_strerror",
+           "dwtfrag_learned_geometry", "dwtfrag_protect_learned", "dwtfrag_restore_learned",
+           "dwtfrag_learned_pairs", "dwtfrag_trainer_workspace_bytes", "dwtfrag_trainer_init",
+           "dwtfrag_trainer_step")
 
 
 def lib():
@@ -78,6 +81,18 @@ def lib():
     L.dwtfrag_aes128_ctr.restype = ctypes.c_int
     L.dwtfrag_strerror.argtypes = [ctypes.c_int]
     L.dwtfrag_strerror.restype = ctypes.c_char_p
+    u64, u32, cp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_char_p
+    L.dwtfrag_learned_geometry.argtypes = [u64, u32, u32, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+    L.dwtfrag_protect_learned.argtypes = [vp, u64, u32, u32, cp, cp, vp, vp, vp, vp, u64, vp]
+    L.dwtfrag_restore_learned.argtypes = [vp, vp, u64, u32, u32, cp, cp, vp, vp, vp, u64, vp]
+    L.dwtfrag_learned_pairs.argtypes = [vp, u64, u32, u32, vp, vp, vp, u64, vp]
+    L.dwtfrag_trainer_workspace_bytes.argtypes = []
+    L.dwtfrag_trainer_workspace_bytes.restype = u64
+    L.dwtfrag_trainer_init.argtypes = [vp, vp, vp]
+    L.dwtfrag_trainer_step.argtypes = [vp, vp, vp, u64, u64, ctypes.c_float, vp, u64, vp]
+    for f in ("dwtfrag_learned_geometry", "dwtfrag_protect_learned", "dwtfrag_restore_learned",
+              "dwtfrag_learned_pairs", "dwtfrag_trainer_init", "dwtfrag_trainer_step"):
+        getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
 

@@ -171,3 +171,17 @@ def mlp_init(n_params: int, seed: int) -> np.ndarray:
     theta[128:144] = 1.0
     theta[160] = 0.0
     return theta.astype(np.float32)
+
+
+def random_predictor(seed: int, weight: int = 128, bias: int = 4000, shift_range=(4, 14)):
+    """Seeded raw integer parameters (w1 16x8, b1 16, w2 16, b2, shift) of the
+    context network, for parity cases: int8 weights uniform in
+    [-weight, weight), biases uniform in [-bias, bias), shift uniform in
+    shift_range."""
+    rng = np.random.default_rng(seed)
+    w1 = rng.integers(-weight, weight, (16, 8)).astype(np.int8)
+    b1 = rng.integers(-bias, bias, 16).astype(np.int32)
+    w2 = rng.integers(-weight, weight, 16).astype(np.int8)
+    b2 = int(rng.integers(-bias, bias))
+    shift = int(rng.integers(shift_range[0], shift_range[1]))
+    return w1, b1, w2, b2, shift
