@@ -129,7 +129,7 @@ def test_int16_bound_holds_and_fits():
     rng = np.random.default_rng(8)
     worst = 0
     for _ in range(6):
-        net = rand_net(rng, bias=2 ** 20, shift=0)      # corrections saturate
+        net = rand_net(rng, bias=2 ** 16, shift=0)      # corrections saturate
         a = np.where(rng.random((48, 48)) < 0.5, 0, 255)
         ll, det = L.fwd_multilevel(a, 3, net)
         worst = max(worst, np.abs(ll).max(), *(np.abs(b).max() for lv in det for b in lv))
