@@ -91,7 +91,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", choices=["large", "small"], default="large")
+    ap.add_argument("--config", choices=["large", "small", "learned", "serve"], default="large")
+    ap.add_argument("--duration", type=float, default=30.0, help="serve config: seconds of arrivals")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve config: arrivals per second")
+    ap.add_argument("--images", type=int, default=0,
+                    help="learned config: number of 4096x4096 images (default 64)")
     ap.add_argument("--seg-rows", type=int, default=0)
     ap.add_argument("--lane-cols", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -113,6 +117,11 @@ def main():
               "(each buffer is independent; see the design notes on sharding).",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.config == "learned":
+        return run_learned(args)
+    if args.config == "serve":
+        return run_serve(args)
 
     import numpy as np
     import torch
@@ -251,6 +260,249 @@ def main():
     if not args.no_cpu_baseline and args.config == "large":
         log("timing the CPU oracle on a bounded sample ...")
         result["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(result), flush=True)
+
+
+def run_serve(args):
+    """Serving workload: Poisson arrivals (seed 5) at --rate per second for
+    --duration seconds; sizes log-uniform in 16 KiB .. 256 MiB drawn from a
+    pool of 256 device-resident buffers (random bytes from a seeded device
+    generator, the default width, 1..4 levels); half the requests protect a
+    pool buffer, half restore its pre-protected fragments."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import paper_1803_04880_amd as dwtfrag
+    import synth
+    from paper_1803_04880_amd import serve
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(5)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    pool = []
+    for i in range(256):
+        n = int(math.exp(rng.uniform(math.log(16 << 10), math.log(256 << 20))))
+        lv = int(rng.integers(1, 5))
+        w = synth.default_width(n)
+        x = torch.randint(0, 256, (n,), dtype=torch.uint8, device=dev, generator=gen)
+        key, nonce = rng.bytes(16), rng.bytes(16)
+        p, q = dwtfrag.protect(x, w, lv, key, nonce)
+        pool.append((n, w, lv, key, nonce, x, p, q))
+    torch.cuda.synchronize()
+    log(f"pool of {len(pool)} buffers, {sum(e[0] for e in pool) / 1e9:.2f} GB")
+    reqs, t = [], 0.0
+    while True:
+        t += float(rng.exponential(1.0 / args.rate))
+        if t >= args.duration:
+            break
+        n, w, lv, key, nonce, x, p, q = pool[int(rng.integers(0, len(pool)))]
+        op = "protect" if rng.random() < 0.5 else "restore"
+        reqs.append(serve.Request(len(reqs), op, t, n, w, lv, key, nonce,
+                                  x=x if op == "protect" else None,
+                                  priv=p if op == "restore" else None,
+                                  pub=q if op == "restore" else None))
+    srv = serve.Server(budget_bytes=64 << 30, max_batch=512)
+    # results are checked (a sample, against the lone calls that made the
+    # pool) and released as requests complete
+    stride = max(1, len(reqs) // 50)
+    checks = []
+
+    def on_complete(r):
+        if r.rid % stride == 0:
+            e = next(e for e in pool if e[3] == r.key and e[4] == r.nonce)
+            if r.op == "protect":
+                checks.append(bool(torch.equal(r.out_priv, e[6]) and torch.equal(r.out_pub, e[7])))
+            else:
+                checks.append(bool(torch.equal(r.out, e[5])))
+        r.out_priv = r.out_pub = r.out = None
+
+    srv.on_complete = on_complete
+    wall = srv.run(reqs)
+    lat = [(r.done - r.arrival) * 1e3 for r in reqs]
+    total = sum(r.n for r in reqs)
+    ok = bool(checks) and all(checks)
+    result = {
+        "metric": "serving: arrival-to-completion latency and sustained GB/s on 1 MI355X",
+        "value": round(total / wall / 1e9, 2), "unit": "GB/s", "n_gpus": 1, "steps": len(reqs),
+        "warmup": 0, "ms_per_step": round(wall / max(len(reqs), 1) * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int16/int32",
+        "data": "synthetic",
+        "config": {"workload": f"Poisson {args.rate:.0f}/s for {args.duration:.0f}s, sizes 16 KiB-256 MiB "
+                               "log-uniform (pool of 256), 50/50 protect/restore, 64 GB budget",
+                   "requests": len(reqs), "offered_gbps": round(total / args.duration / 1e9, 2)},
+        "bit_exact_sample": ok,
+        "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),
+                       "max": round(max(lat), 3)},
+        "launches": srv.batches_launched, "wall_s": round(wall, 3),
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(result), flush=True)
+
+
+def _entropy_bits(pub):
+    """Zeroth-order entropy (bits per coefficient) of int16 coefficients."""
+    import torch
+    counts = torch.bincount((pub.to(torch.int64) + 32768).reshape(-1), minlength=65536)
+    p = counts[counts > 0].double() / pub.numel()
+    return float(-(p * torch.log2(p)).sum())
+
+
+def run_learned(args):
+    """Learned-predictor workload: 64 smooth 4096 x 4096 images (1 GiB), 3
+    levels.  Trains the network on the GPU, then times learned and plain
+    protect + restore over all images with the oracle-trained network of
+    tests/golden (a fixed input, so the fragments can be checked against the
+    oracle's digest)."""
+    import multiprocessing
+
+    import torch
+
+    import paper_1803_04880_amd as dwtfrag
+    import synth
+    from paper_1803_04880_amd import learned as GL
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    steps = args.steps if args.steps != 50 else 10
+    warmup = args.warmup if args.warmup != 5 else 2
+    nimg = args.images or synth.LEARNED_IMAGES
+    W, L, n = 4096, 3, 4096 * 4096
+    t0 = time.time()
+    with multiprocessing.get_context("fork").Pool(8) as pool:
+        imgs = pool.map(synth.learned_image, range(nimg))
+    log(f"{nimg} images of 4096x4096 generated in {time.time() - t0:.1f}s")
+    xs = [torch.from_numpy(im).to(dev) for im in imgs]
+    del imgs
+    kn = [synth.learned_key_nonce(i) for i in range(nimg)]
+    with open(os.path.join(ROOT, "tests", "golden", "predictor_smooth.json")) as f:
+        rec = json.load(f)
+    gold_net = GL.Predictor.from_arrays(rec["w1"], rec["b1"], rec["w2"], rec["b2"], rec["shift"])
+    g = dwtfrag.geometry(n, W, L)
+    privs = [torch.empty(g["priv_bytes"], dtype=torch.uint8, device=dev) for _ in range(nimg)]
+    pubs = [torch.empty(g["pub_bytes"] // 2, dtype=torch.int16, device=dev) for _ in range(nimg)]
+    outs = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(nimg)]
+    ws = GL.workspace(n, W, L, dev)
+
+    def protect_all(net):
+        for i in range(nimg):
+            GL.protect(xs[i], W, L, kn[i][0], kn[i][1], net, priv=privs[i], pub=pubs[i], ws=ws)
+
+    def restore_all(net):
+        for i in range(nimg):
+            GL.restore(privs[i], pubs[i], n, W, L, kn[i][0], kn[i][1], net, out=outs[i], ws=ws)
+
+    def plain_protect_all():
+        for i in range(nimg):
+            dwtfrag.protect(xs[i], W, L, kn[i][0], kn[i][1], priv=privs[i], pub=pubs[i])
+
+    def plain_restore_all():
+        for i in range(nimg):
+            dwtfrag.restore(privs[i], pubs[i], n, W, L, kn[i][0], kn[i][1], out=outs[i])
+
+    # parity: image 0 against the oracle's digest, every image round trips
+    protect_all(gold_net)
+    restore_all(gold_net)
+    torch.cuda.synchronize()
+    with open(os.path.join(ROOT, "tests", "golden", "oracle_digests.json")) as f:
+        gold = json.load(f)["learned"]
+    bit_exact = hashlib.sha256(privs[0].cpu().numpy().tobytes()).hexdigest() == gold["priv_sha256"]
+    bit_exact &= hashlib.sha256(pubs[0].cpu().numpy().tobytes()).hexdigest() == gold["pub_sha256"]
+    bit_exact &= all(bool(torch.equal(outs[i], xs[i])) for i in range(nimg))
+    log(f"parity vs oracle (image 0) and round trips: {'bit-exact' if bit_exact else 'MISMATCH'}")
+    ent_learned = sum(_entropy_bits(p) for p in pubs) / nimg
+
+    # training on the GPU: pairs of the 512x512 image and of rows 0..256 of
+    # the 256 MiB workload, the recipe of the stored network
+    small = synth.config_small()["buf"]
+    big = synth.config_large()
+    part = big["buf"][:256 * big["width"]].copy()
+    del big
+    c1, t1 = GL.training_pairs(torch.from_numpy(small).to(dev), 512, 3)
+    c2, t2 = GL.training_pairs(torch.from_numpy(part).to(dev), 32768, 3)
+    ctx, tgt = torch.cat([c1, c2]), torch.cat([t1, t2])
+    trainer = GL.Trainer(synth.mlp_init(161, 4), dev)
+    nb = max(tgt.numel() // 65536, 1)
+    torch.cuda.synchronize()
+    tt0 = time.perf_counter()
+    for s_ in range(300):
+        trainer.step(ctx, tgt, 0.01, s_ % nb, nb)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - tt0
+    st = trainer.read()
+    gpu_net = GL.Predictor.from_buffer_copy(bytes(st.net))
+    # entropy with the GPU-trained network, round trip checked
+    protect_all(gpu_net)
+    torch.cuda.synchronize()
+    ent_gpu = sum(_entropy_bits(p) for p in pubs) / nimg
+    restore_all(gpu_net)
+    torch.cuda.synchronize()
+    bit_exact &= all(bool(torch.equal(outs[i], xs[i])) for i in range(nimg))
+
+    stream = torch.cuda.current_stream()
+
+    def timed(fp, fr):
+        for _ in range(warmup):
+            fp()
+            fr()
+        torch.cuda.synchronize()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        w0 = time.perf_counter()
+        for k in range(steps):
+            ev[k][0].record(stream)
+            fp()
+            ev[k][1].record(stream)
+            fr()
+            ev[k][2].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        tp = [ev[k][0].elapsed_time(ev[k][1]) * 1e3 for k in range(steps)]
+        tr = [ev[k][1].elapsed_time(ev[k][2]) * 1e3 for k in range(steps)]
+        return wall, tp, tr
+
+    plain_protect_all()
+    torch.cuda.synchronize()
+    ent_plain = sum(_entropy_bits(p) for p in pubs) / nimg
+    wall_p, tp_p, tr_p = timed(plain_protect_all, plain_restore_all)
+    wall, tp, tr = timed(lambda: protect_all(gold_net), lambda: restore_all(gold_net))
+    total = n * nimg
+    value = total * steps / wall / 1e9
+    # ALU roofline of the learned passes: int8 multiply-accumulates of the
+    # network (8x16 + 16 per predicted sample) over all predict steps of both
+    # directions, against the v_dot4 rate (4 MACs per lane per cycle)
+    _, pairs = GL.learned_geometry(n, W, L)
+    macs = 2 * pairs * 144 * nimg
+    pair_us = (sum(tp) + sum(tr)) / steps
+    achieved = macs / (pair_us * 1e-6) / 1e12
+    peak = 256 * 64 * 2.4e9 * 4 / 1e12
+    result = {
+        "metric": "learned-predictor protect+restore GB/s on 1 MI355X, bit-exact",
+        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": round(wall / steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int8/int32", "data": "synthetic",
+        "config": {"workload": f"{nimg} smooth 4096x4096 images ({total / 2**30:.2f} GiB), 3 levels, "
+                               "context network trained by the oracle", "images": nimg,
+                   "width": W, "levels": L},
+        "bit_exact": bool(bit_exact),
+        "latency_us": {"protect_all_p50": round(percentile(tp, 50), 1),
+                       "restore_all_p50": round(percentile(tr, 50), 1)},
+        "plain_53": {"value": round(total * steps / wall_p / 1e9, 2), "unit": "GB/s",
+                     "protect_all_p50_us": round(percentile(tp_p, 50), 1),
+                     "restore_all_p50_us": round(percentile(tr_p, 50), 1)},
+        "entropy_bits": {"plain_53": round(ent_plain, 4), "learned_oracle_net": round(ent_learned, 4),
+                         "learned_gpu_trained": round(ent_gpu, 4)},
+        "training": {"pairs": int(tgt.numel()), "steps": 300, "seconds": round(train_s, 3),
+                     "final_batch_loss": round(float(st.loss), 4),
+                     "oracle_loss_end_full_set": rec["loss_end"]},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 1),
+                     "unit": "TMAC/s (int8 dot4)", "frac": round(achieved / peak, 4),
+                     "traffic": None, "kernel": "all learned passes of protect+restore",
+                     "macs_per_step": macs},
+        "cpu_baseline": None,
+    }
     print(json.dumps(result), flush=True)
 
 

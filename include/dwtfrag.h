@@ -124,6 +124,76 @@ int dwtfrag_aes128_ctr(const uint8_t *in, uint8_t *out, uint64_t nbytes,
                        uint64_t first_block, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Batches of independent buffers (the thesis cuts data into many fixed-size
+ * chunks, Ch. 5 section 5.2.1, and feeds many chunks per GPU call).  A batch
+ * is planned once on the host, copied into a caller-owned device buffer, and
+ * run by persistent launches that drain one tile queue per kernel shape, so
+ * buffers of uneven sizes share the device.  Each item's fragments are
+ * exactly those of dwtfrag_protect on that item alone.  The run calls launch
+ * kernels only (no allocation, copy or memset): they can be captured in a
+ * HIP graph and replayed.  Calls on one plan must be ordered on one stream.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+  const uint8_t *in;       /* device, n bytes (protect input), 16-byte aligned */
+  uint8_t *out;            /* device, n bytes (restore output) or NULL */
+  uint8_t *priv;           /* device, geometry priv_bytes, 16-byte aligned */
+  int16_t *pub;            /* device, geometry pub_bytes / 2 values (NULL if 0) */
+  uint64_t n;
+  uint32_t width;
+  uint32_t levels;         /* 1..4 */
+  uint8_t key[16];
+  uint8_t nonce[16];
+} dwtfrag_item;
+
+/* A launch shape for the buffers of one (width, levels) class, as chosen by
+ * dwtfrag_autotune. */
+typedef struct {
+  uint32_t width, levels;
+  dwtfrag_launch launch;
+} dwtfrag_tune_entry;
+
+typedef struct dwtfrag_batch dwtfrag_batch;  /* opaque host-side plan */
+
+/* Host only: plan `count` items (host array, read before return).  Items of a
+ * (width, levels) class listed in `tune` use that launch shape, others
+ * 128-row tiles.  *out receives a plan owned by the caller (free it with
+ * dwtfrag_batch_destroy).  EINVAL for a null or misaligned pointer, levels
+ * outside 1..4; ERANGE for geometry out of range or more than 8 kernel
+ * shapes. */
+int dwtfrag_batch_create(const dwtfrag_item *items, uint32_t count,
+                         const dwtfrag_tune_entry *tune, uint32_t n_tune,
+                         dwtfrag_batch **out);
+
+/* Device bytes the plan needs (256-byte aligned buffer). */
+uint64_t dwtfrag_batch_device_bytes(const dwtfrag_batch *plan);
+
+/* Copy the plan's tables into `device_plan` (device, 256-byte aligned, at
+ * least dwtfrag_batch_device_bytes) on `stream`, and wait for the copy.  The
+ * buffer must stay allocated and untouched while the plan is used. */
+int dwtfrag_batch_upload(dwtfrag_batch *plan, void *device_plan, uint64_t device_bytes,
+                         void *stream);
+
+/* Protect every item (fragments as dwtfrag_protect), or restore every item
+ * (outputs as dwtfrag_restore; every item needs `out`). */
+int dwtfrag_batch_protect(const dwtfrag_batch *plan, void *stream);
+int dwtfrag_batch_restore(const dwtfrag_batch *plan, void *stream);
+
+void dwtfrag_batch_destroy(dwtfrag_batch *plan);
+
+/* Autotuner: time protect + restore of one buffer (device `in`, n bytes)
+ * under each candidate launch shape (rows per tile 0 = the single-buffer
+ * default, 64, 128, 256; 8 and 16 columns per lane where the levels allow),
+ * `trials` times each, with HIP events on `stream`, and return the fastest in
+ * *best (and its time in microseconds in *best_us).  `scratch` (device) holds
+ * the fragments, the output and the workspace: at least
+ * geom.priv_bytes + geom.pub_bytes + n + geom.workspace_bytes + 768 bytes.
+ * Synchronises `stream`. */
+int dwtfrag_autotune(const uint8_t *in, uint64_t n, uint32_t width, uint32_t levels,
+                     void *scratch, uint64_t scratch_bytes, uint32_t trials,
+                     dwtfrag_launch *best, float *best_us, void *stream);
+
+/* ------------------------------------------------------------------------
  * Learned predictor (an extension of the predict slot of the Ch. 5 section
  * 5.1.1 lifting, eq. (5.1); judged by the entropy of eq. (5.6)).  At an odd
  * position i of a signal x of length N >= 2, m the whole-sample mirror:

@@ -361,3 +361,26 @@ def train(theta0, ctx, target, steps, lr, batch):
         _, g = loss_grad(fake_quant(theta), ctx[i::nb], target[i::nb])
         theta, m, v = adam_step(theta, g, m, v, step, lr)
     return theta
+
+
+# ----------------------------------------------------------- fragments --
+
+def protect(buf, width, levels, key, nonce, net: Predictor):
+    """(priv, pub) fragments with the learned lifting: the plain fragment
+    layout and AES-128-CTR of ``fragment.protect``, this module's transform."""
+    from . import aes128, fragment
+    mat = fragment.view(buf, width)
+    ll, details = fwd_multilevel(mat, levels, net)
+    priv_plain, pub = fragment.serialize(ll, details)
+    return aes128.ctr_xor(key, nonce, priv_plain).tobytes(), pub
+
+
+def restore(priv, pub, n, width, levels, key, nonce, net: Predictor):
+    """The first n bytes (each sample modulo 256) from learned fragments."""
+    from . import aes128, fragment
+    geom = fragment.geometry(n, width, levels)
+    if len(priv) != geom["priv_bytes"] or len(pub) != geom["pub_bytes"]:
+        raise ValueError("fragment sizes do not match the geometry")
+    ll, details = fragment.deserialize(aes128.ctr_xor(key, nonce, priv).tobytes(), pub, geom)
+    mat = inv_multilevel(ll, details, net)
+    return (mat.reshape(-1)[:n] & 0xFF).astype(np.uint8).tobytes()

@@ -50,7 +50,10 @@ EXPORTS = ("dwtfrag_geometry", "dwtfrag_default_width", "dwtfrag_protect", "dwtf
            "dwtfrag_aes128_ctr", "dwtfrag_strerror",
            "dwtfrag_learned_geometry", "dwtfrag_protect_learned", "dwtfrag_restore_learned",
            "dwtfrag_learned_pairs", "dwtfrag_trainer_workspace_bytes", "dwtfrag_trainer_init",
-           "dwtfrag_trainer_step")
+           "dwtfrag_trainer_step",
+           "dwtfrag_batch_create", "dwtfrag_batch_device_bytes", "dwtfrag_batch_upload",
+           "dwtfrag_batch_protect", "dwtfrag_batch_restore", "dwtfrag_batch_destroy",
+           "dwtfrag_autotune")
 
 
 def lib():
@@ -92,6 +95,19 @@ def lib():
     L.dwtfrag_trainer_step.argtypes = [vp, vp, vp, u64, u64, ctypes.c_float, vp, u64, vp]
     for f in ("dwtfrag_learned_geometry", "dwtfrag_protect_learned", "dwtfrag_restore_learned",
               "dwtfrag_learned_pairs", "dwtfrag_trainer_init", "dwtfrag_trainer_step"):
+        getattr(L, f).restype = ctypes.c_int
+    L.dwtfrag_batch_create.argtypes = [vp, u32, vp, u32, ctypes.POINTER(vp)]
+    L.dwtfrag_batch_device_bytes.argtypes = [vp]
+    L.dwtfrag_batch_device_bytes.restype = u64
+    L.dwtfrag_batch_upload.argtypes = [vp, vp, u64, vp]
+    L.dwtfrag_batch_protect.argtypes = [vp, vp]
+    L.dwtfrag_batch_restore.argtypes = [vp, vp]
+    L.dwtfrag_batch_destroy.argtypes = [vp]
+    L.dwtfrag_batch_destroy.restype = None
+    L.dwtfrag_autotune.argtypes = [vp, u64, u32, u32, vp, u64, u32, ctypes.POINTER(Launch),
+                                   ctypes.POINTER(ctypes.c_float), vp]
+    for f in ("dwtfrag_batch_create", "dwtfrag_batch_upload", "dwtfrag_batch_protect",
+              "dwtfrag_batch_restore", "dwtfrag_autotune"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L

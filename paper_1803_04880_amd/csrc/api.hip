@@ -3,6 +3,7 @@
 #include "dwtfrag.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <vector>
 
@@ -16,6 +17,8 @@ hipError_t launch_inv(int L, int C1, bool u8out, const int16_t *llin, const int1
                       void *out, const StageParams &P, hipStream_t s);
 hipError_t launch_ctr(const uint8_t *in, uint8_t *out, uint64_t nbytes, const AesKey &key,
                       uint64_t first_block, hipStream_t s);
+int fwd_waves_per_cu(int L, int C1, bool u8in);
+int inv_waves_per_cu(int L, int C1, bool u8out);
 
 static constexpr AesTables kHostTables = make_aes_tables();
 
@@ -108,6 +111,28 @@ void level_offsets(const Geometry &g, uint32_t l, int64_t *hl, int64_t *lh, int6
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
+// Wavefronts the current device keeps resident at once for the kernel of a
+// stage: compute units x resident wavefronts per CU (queried once per device
+// and kernel variant; falls back to 256 x 16 if the queries fail).
+int64_t device_slots(bool forward, int L, int C1, bool bytes) {
+  constexpr int kDev = 16, kVar = 2 * 5 * 2 * 2;
+  static std::atomic<int> cache[kDev][kVar];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDev) dev = -1;
+  const int var = ((forward ? 1 : 0) * 5 + L) * 4 + (C1 == 16 ? 2 : 0) + (bytes ? 1 : 0);
+  if (dev >= 0) {
+    const int v = cache[dev][var].load(std::memory_order_relaxed);
+    if (v > 0) return v;
+  }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev < 0 ? 0 : dev) != hipSuccess)
+    cus = 0;
+  const int per_cu = forward ? fwd_waves_per_cu(L, C1, bytes) : inv_waves_per_cu(L, C1, bytes);
+  const int slots = (cus > 0 && per_cu > 0) ? cus * per_cu : 256 * 16;
+  if (dev >= 0) cache[dev][var].store(slots, std::memory_order_relaxed);
+  return slots;
+}
+
 // Fill stage s's parameters.  forward selects the halo shape of the direction.
 int plan_stage(const Geometry &g, int s, bool forward, const dwtfrag_launch *launch,
                const AesKey &key, StageParams *P, int *L_out, int *C1_out) {
@@ -144,19 +169,20 @@ int plan_stage(const Geometry &g, int s, bool forward, const dwtfrag_launch *lau
   P->halo_t = forward ? (1 << (L + 1)) : (1 << L);
   P->halo_b = 1 << L;
   const int unit = 1 << L;
-  int own_h;
+  P->unit_rows = unit;
+  P->units = (P->H + unit - 1) / unit;
+  int64_t n_seg;
   if (launch && launch->seg_rows) {
-    own_h = round_up(int(std::min<uint32_t>(launch->seg_rows, uint32_t(P->H))), unit);
+    const int own_h = std::max(unit, round_up(int(std::min<uint32_t>(launch->seg_rows, uint32_t(P->H))), unit));
+    n_seg = (P->H + own_h - 1) / own_h;
   } else {
-    const int64_t target_waves = 4096;
-    int64_t want = (int64_t(P->H) * P->n_win + target_waves - 1) / target_waves;
-    want = std::max<int64_t>(want, 2 * unit);
-    want = std::max<int64_t>(want, std::min<int64_t>(64, P->H));
-    own_h = round_up(int(std::min<int64_t>(want, P->H)), unit);
+    // one round of resident wavefronts: as many segments as fill the device
+    // once, each at least two units long (halo work stays below the owned)
+    const int64_t slots = device_slots(forward, L, C1, s == 0);
+    n_seg = std::max<int64_t>(1, slots / P->n_win);
+    n_seg = std::min<int64_t>(n_seg, std::max(1, P->units / 2));
   }
-  own_h = std::max(own_h, unit);
-  P->own_h = own_h;
-  P->n_seg = (P->H + own_h - 1) / own_h;
+  P->n_seg = int32_t(std::min<int64_t>(std::max<int64_t>(n_seg, 1), P->units));
   const int64_t waves = int64_t(P->n_win) * P->n_seg;
   if (waves > (int64_t(1) << 30)) return DWTFRAG_ERANGE;
   P->n_waves = int32_t(waves);
@@ -178,6 +204,18 @@ int plan_stage(const Geometry &g, int s, bool forward, const dwtfrag_launch *lau
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 }  // namespace
+
+// Plan of a buffer whose levels fit one fused stage (levels <= kMaxFused).
+int plan_single_stage(uint64_t n, uint32_t width, uint32_t levels, bool forward,
+                      const dwtfrag_launch *launch, const AesKey &key, StageParams *P, int *L,
+                      int *C1, uint64_t *priv_bytes) {
+  if (levels > uint32_t(kMaxFused)) return DWTFRAG_EINVAL;
+  Geometry g;
+  const int rc = make_geometry(n, width, levels, &g);
+  if (rc != DWTFRAG_OK) return rc;
+  *priv_bytes = g.priv_bytes;
+  return plan_stage(g, 0, forward, launch, key, P, L, C1);
+}
 }  // namespace dwtfrag
 
 using namespace dwtfrag;
@@ -286,6 +324,73 @@ int dwtfrag_aes128_ctr(const uint8_t *in, uint8_t *out, uint64_t nbytes, const u
   expand_key(key, nonce, &k);
   if (launch_ctr(in, out, nbytes, k, first_block, static_cast<hipStream_t>(stream)) != hipSuccess)
     return DWTFRAG_EDEVICE;
+  return DWTFRAG_OK;
+}
+
+int dwtfrag_autotune(const uint8_t *in, uint64_t n, uint32_t width, uint32_t levels,
+                     void *scratch, uint64_t scratch_bytes, uint32_t trials,
+                     dwtfrag_launch *best, float *best_us, void *stream) {
+  if (!in || !scratch || !best || trials == 0) return DWTFRAG_EINVAL;
+  Geometry g;
+  int rc = make_geometry(n, width, levels, &g);
+  if (rc != DWTFRAG_OK) return rc;
+  const uint64_t o_pub = align256(g.priv_bytes);
+  const uint64_t o_out = o_pub + align256(g.pub_bytes);
+  const uint64_t o_ws = o_out + align256(n);
+  if (scratch_bytes < o_ws + g.ws_bytes || (reinterpret_cast<uintptr_t>(scratch) & 255))
+    return DWTFRAG_EWORKSPACE;
+  char *base = static_cast<char *>(scratch);
+  uint8_t *priv = reinterpret_cast<uint8_t *>(base);
+  int16_t *pub = g.pub_bytes ? reinterpret_cast<int16_t *>(base + o_pub) : nullptr;
+  uint8_t *out = reinterpret_cast<uint8_t *>(base + o_out);
+  void *ws = g.ws_bytes ? base + o_ws : nullptr;
+  const uint8_t key[16] = {0}, nonce[16] = {0};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return DWTFRAG_EDEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return DWTFRAG_EDEVICE;
+  }
+  float best_t = -1.0f;
+  dwtfrag_launch best_l{0, 0};
+  const uint32_t rows[] = {0, 64, 128, 256};
+  const uint32_t cols[] = {8, 16};
+  rc = DWTFRAG_OK;
+  for (uint32_t c : cols) {
+    if (levels % kMaxFused == 0 && c == 8) continue;  // a four-level stage needs 16 columns
+    for (uint32_t r : rows) {
+      const dwtfrag_launch ln{r, c};
+      // one untimed pair, then `trials` timed pairs
+      if (dwtfrag_protect(in, n, width, levels, key, nonce, priv, pub, ws, g.ws_bytes, &ln, st) ||
+          dwtfrag_restore(priv, pub, n, width, levels, key, nonce, out, ws, g.ws_bytes, &ln, st)) {
+        rc = DWTFRAG_EDEVICE;
+        break;
+      }
+      hipEventRecord(e0, st);
+      for (uint32_t t = 0; t < trials; ++t) {
+        dwtfrag_protect(in, n, width, levels, key, nonce, priv, pub, ws, g.ws_bytes, &ln, st);
+        dwtfrag_restore(priv, pub, n, width, levels, key, nonce, out, ws, g.ws_bytes, &ln, st);
+      }
+      hipEventRecord(e1, st);
+      float ms = 0.0f;
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = DWTFRAG_EDEVICE;
+        break;
+      }
+      const float us = 1000.0f * ms / float(trials);
+      if (best_t < 0.0f || us < best_t) {
+        best_t = us;
+        best_l = ln;
+      }
+    }
+    if (rc != DWTFRAG_OK) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != DWTFRAG_OK) return rc;
+  *best = best_l;
+  if (best_us) *best_us = best_t;
   return DWTFRAG_OK;
 }
 

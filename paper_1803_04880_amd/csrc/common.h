@@ -140,15 +140,18 @@ __device__ __forceinline__ void load_aes_tables(uint32_t *te, uint32_t *kw, cons
 
 // --------------------------------------------------------- launch geometry --
 // One stage = up to kMaxFused levels over an H x W input.  Wavefronts own
-// rectangles of the level-0 grid: window k owns columns [k*own_w, ...),
-// segment s owns rows [s*own_h, ...).
+// rectangles of the level-0 grid: window k owns columns [k*own_w, ...);
+// the rows are cut into `units` units of unit_rows = 2^L rows, and segment s
+// owns units [floor(s*units/n_seg), floor((s+1)*units/n_seg)), so segment
+// lengths differ by at most one unit.
 struct StageParams {
   int64_t n_valid;            // valid input elements (byte view: n; else H*W)
   int32_t H, W;               // stage input dims
   int32_t hdim[kMaxFused + 1], wdim[kMaxFused + 1];  // level dims, [0] = input
   int64_t off_hl[kMaxFused + 1], off_lh[kMaxFused + 1], off_hh[kMaxFused + 1];
   int32_t own_w, n_win;       // owned columns per window, number of windows
-  int32_t own_h, n_seg;       // owned rows per segment, number of segments
+  int32_t unit_rows, units;   // 2^L, ceil(H / 2^L)
+  int32_t n_seg;              // number of row segments
   int32_t halo_l;             // columns before the owned range (multiple of lane_cols)
   int32_t halo_t, halo_b;     // rows streamed before / after the owned range
   int32_t n_waves;
@@ -156,6 +159,11 @@ struct StageParams {
   int32_t ks_rows, ks_blocks; // keystream ring: rows per refill, blocks per row
   AesKey key;
 };
+
+// First level-0 row of segment s (s == n_seg gives units * unit_rows).
+__device__ __forceinline__ int seg_start(const StageParams &P, int s) {
+  return P.unit_rows * int((int64_t(s) * P.units) / P.n_seg);
+}
 
 // ------------------------------------------------------- wavefront taps --
 // wave_shl:1 -> lane i receives lane i+1; wave_shr:1 -> lane i receives

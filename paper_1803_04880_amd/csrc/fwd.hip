@@ -19,6 +19,7 @@
 // l+1's queue (or, at the last level, to the LL output), detail rows inside the
 // owned rectangle are stored.  Rows a level cannot pair yet stay in registers
 // until the next batch.
+#include "batch.h"
 #include "lift.h"
 #include "pack.h"
 
@@ -321,11 +322,11 @@ struct FwdWave {
     const int win = wave % G.n_win;
     const int seg = wave / G.n_win;
     X0 = win * G.own_w;
-    Y0 = seg * G.own_h;
     last_win = (win == G.n_win - 1);
     last_seg = (seg == G.n_seg - 1);
+    Y0 = seg_start(G, seg);
     X1 = last_win ? G.W : X0 + G.own_w;
-    Y1 = last_seg ? G.H : Y0 + G.own_h;
+    Y1 = last_seg ? G.H : seg_start(G, seg + 1);
     const int cbase = (win == 0) ? 0 : X0 - G.halo_l;
     c0 = cbase + lane * C1;
     r0 = Y0 > G.halo_t ? Y0 - G.halo_t : 0;
@@ -416,6 +417,66 @@ static hipError_t launch_fwd_t(const void *in, int16_t *pub, int16_t *llout, con
   hipLaunchKernelGGL((fwd_kernel<L, C1, U8IN>), dim3(blocks), dim3(kBlockThreads), 0, s, in, pub,
                      llout, P);
   return hipGetLastError();
+}
+
+// Batch form: a persistent launch drains one class's tile queue; each tile
+// is one wavefront rectangle of one item (the item's own plan and buffers).
+template <int L, int C1>
+__global__ __launch_bounds__(kBlockThreads) void fwd_batch_kernel(const BatchItem *__restrict__ items,
+                                                                  const int2 *__restrict__ tiles,
+                                                                  int64_t n_tiles,
+                                                                  unsigned int *__restrict__ head) {
+  using W = FwdWave<L, C1, true>;
+  __shared__ uint32_t s_lds[kWavesPerBlock][W::kLdsWords];
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    unsigned int t = 0;
+    if (lane == 0) t = atomicAdd(head, 1u);
+    t = __builtin_amdgcn_readfirstlane(t);
+    if (int64_t(t) >= n_tiles) break;
+    const int2 e = tiles[t];
+    const BatchItem &it = items[e.x];
+    W w{it.fwd};
+    w.in8 = it.in;
+    w.in16 = nullptr;
+    w.pub = it.pub;
+    w.llout = reinterpret_cast<int16_t *>(it.priv);
+    w.lds = s_lds[wib];
+    w.lane = lane;
+    w.run(e.y);
+    wave_lds_sync();
+  }
+}
+
+hipError_t launch_fwd_batch(int L, int C1, const BatchItem *items, const int2 *tiles, int64_t n_tiles,
+                            unsigned int *head, int blocks, hipStream_t s) {
+#define DWTFRAG_CASE(LL, CC)                                                                    \
+  if (L == LL && C1 == CC) {                                                                    \
+    hipLaunchKernelGGL((fwd_batch_kernel<LL, CC>), dim3(blocks), dim3(kBlockThreads), 0, s,     \
+                       items, tiles, n_tiles, head);                                            \
+    return hipGetLastError();                                                                   \
+  }
+  DWTFRAG_CASE(1, 8) DWTFRAG_CASE(2, 8) DWTFRAG_CASE(3, 8)
+  DWTFRAG_CASE(1, 16) DWTFRAG_CASE(2, 16) DWTFRAG_CASE(3, 16) DWTFRAG_CASE(4, 16)
+#undef DWTFRAG_CASE
+  return hipErrorInvalidValue;
+}
+
+// Resident wavefronts per CU of the forward kernel for (L, C1).
+int fwd_waves_per_cu(int L, int C1, bool u8in) {
+  const void *fn = nullptr;
+#define DWTFRAG_FN(LL, CC)                                                              \
+  if (L == LL && C1 == CC)                                                              \
+    fn = u8in ? reinterpret_cast<const void *>(&fwd_kernel<LL, CC, true>)               \
+              : reinterpret_cast<const void *>(&fwd_kernel<LL, CC, false>);
+  DWTFRAG_FN(1, 8) DWTFRAG_FN(2, 8) DWTFRAG_FN(3, 8)
+  DWTFRAG_FN(1, 16) DWTFRAG_FN(2, 16) DWTFRAG_FN(3, 16) DWTFRAG_FN(4, 16)
+#undef DWTFRAG_FN
+  int blocks = 0;
+  if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kBlockThreads, 0) != hipSuccess)
+    return 0;
+  return blocks * kWavesPerBlock;
 }
 
 hipError_t launch_fwd(int L, int C1, bool u8in, const void *in, int16_t *pub, int16_t *llout,

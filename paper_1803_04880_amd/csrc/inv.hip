@@ -8,6 +8,7 @@
 // detail rows k of HL_l / LH_l / HH_l and emits rows 2k-1 and 2k of the
 // level-(l-1) grid, which are inverted horizontally and become LL_(l-1) rows
 // for level l-1.  Level 1 emits output rows.
+#include "batch.h"
 #include "lift.h"
 
 namespace dwtfrag {
@@ -27,6 +28,14 @@ struct InvWave {
   int X0, Y0, X1, Y1;
   bool last_win, last_seg;
 
+  // detail rows of the next step of each level, loaded one step ahead
+  template <int l> static constexpr int U = (C<l> / 2) > 0 ? C<l> / 2 : 1;
+  template <int l> static constexpr int RWd = Raw<U<l>>::W;
+  uint32_t Fh1[RWd<1>], Fl1[RWd<1>], Fx1[RWd<1>];
+  uint32_t Fh2[RWd<2>], Fl2[RWd<2>], Fx2[RWd<2>];
+  uint32_t Fh3[RWd<3>], Fl3[RWd<3>], Fx3[RWd<3>];
+  uint32_t Fh4[RWd<4>], Fl4[RWd<4>], Fx4[RWd<4>];
+
   int Dp1[C<1>], Xp1[C<1>];
   int Dp2[C1 >= 2 ? C<2> : 1], Xp2[C1 >= 2 ? C<2> : 1];
   int Dp3[C1 >= 4 ? C<3> : 1], Xp3[C1 >= 4 ? C<3> : 1];
@@ -42,6 +51,34 @@ struct InvWave {
     if constexpr (l == 1) return Xp1; else if constexpr (l == 2) return Xp2;
     else if constexpr (l == 3) return Xp3; else return Xp4;
   }
+  template <int l> __device__ auto &Fh() {
+    if constexpr (l == 1) return Fh1; else if constexpr (l == 2) return Fh2;
+    else if constexpr (l == 3) return Fh3; else return Fh4;
+  }
+  template <int l> __device__ auto &Fl() {
+    if constexpr (l == 1) return Fl1; else if constexpr (l == 2) return Fl2;
+    else if constexpr (l == 3) return Fl3; else return Fl4;
+  }
+  template <int l> __device__ auto &Fx() {
+    if constexpr (l == 1) return Fx1; else if constexpr (l == 2) return Fx2;
+    else if constexpr (l == 3) return Fx3; else return Fx4;
+  }
+
+  // Issue the loads of step k's detail rows of level l (HL_l row k; LH_l and
+  // HH_l row k when they exist), to be consumed by that step.
+  template <int l> __device__ __forceinline__ void prefetch(int k) {
+    constexpr int UU = C<l> / 2;
+    const int N = P.hdim[l - 1];
+    const int Nw = P.wdim[l - 1];
+    const int wl = P.wdim[l];
+    const int bc = c0 >> l;
+    if (k < P.hdim[l])
+      load_raw<UU>(pub + P.off_hl[l], int64_t(k) * (Nw - wl) + bc, (Nw - wl) - bc, Fh<l>());
+    if (2 * k + 1 < N) {
+      load_raw<UU>(pub + P.off_lh[l], int64_t(k) * wl + bc, wl - bc, Fl<l>());
+      load_raw<UU>(pub + P.off_hh[l], int64_t(k) * (Nw - wl) + bc, (Nw - wl) - bc, Fx<l>());
+    }
+  }
 
   // Row i of the level-(l-1) grid after the vertical inverse of level l:
   // undo the horizontal pass, then hand it down.
@@ -55,7 +92,9 @@ struct InvWave {
       if (c0 < X0 || (!last_win && c0 >= X1)) return;
       const int64_t idx = int64_t(i) * P.W + c0;
       if constexpr (U8OUT) {
-        const int64_t lim = min(int64_t(P.W - c0), P.n_valid - int64_t(i) * P.W);
+        // bytes of this lane's columns inside the view: the row's end, and n
+        // (the last row may be partial)
+        const int64_t lim = min(int64_t(P.W - c0), P.n_valid - idx);
         if (lim >= C1 && (idx & (C1 - 1)) == 0) {
           uint32_t w[C1 / 4];
 #pragma unroll
@@ -82,11 +121,8 @@ struct InvWave {
     constexpr int CC = C<l>;
     constexpr int U = CC / 2;
     const int N = P.hdim[l - 1];
-    const int Nw = P.wdim[l - 1];
-    const int wl = P.wdim[l];
-    const int bc = c0 >> l;
     int hl[U];
-    load_i16<U>(pub + P.off_hl[l], int64_t(k) * (Nw - wl) + bc, (Nw - wl) - bc, hl);
+    unpack_raw<U>(Fh<l>(), hl);
     int S[CC];
 #pragma unroll
     for (int u = 0; u < U; ++u) { S[2 * u] = ll[u]; S[2 * u + 1] = hl[u]; }
@@ -102,14 +138,15 @@ struct InvWave {
       const bool has_d = (2 * k + 1 < N);
       if (has_d) {
         int lh[U], hh[U];
-        load_i16<U>(pub + P.off_lh[l], int64_t(k) * wl + bc, wl - bc, lh);
-        load_i16<U>(pub + P.off_hh[l], int64_t(k) * (Nw - wl) + bc, (Nw - wl) - bc, hh);
+        unpack_raw<U>(Fl<l>(), lh);
+        unpack_raw<U>(Fx<l>(), hh);
 #pragma unroll
         for (int u = 0; u < U; ++u) { Dn[2 * u] = lh[u]; Dn[2 * u + 1] = hh[u]; }
       } else {  // odd length, last step: d(N) = d(N-2)
 #pragma unroll
         for (int t = 0; t < CC; ++t) Dn[t] = Dv[t];
       }
+      prefetch<l>(k + 1);
       const bool top = (k == 0);
 #pragma unroll
       for (int t = 0; t < CC; ++t) {
@@ -143,11 +180,11 @@ struct InvWave {
     const int win = wave % P.n_win;
     const int seg = wave / P.n_win;
     X0 = win * P.own_w;
-    Y0 = seg * P.own_h;
     last_win = (win == P.n_win - 1);
     last_seg = (seg == P.n_seg - 1);
+    Y0 = seg_start(P, seg);
     X1 = last_win ? P.W : X0 + P.own_w;
-    Y1 = last_seg ? P.H : Y0 + P.own_h;
+    Y1 = last_seg ? P.H : seg_start(P, seg + 1);
     const int cbase = (win == 0) ? 0 : X0 - P.halo_l;
     c0 = cbase + lane * C1;
     const int kbeg = (Y0 > P.halo_t ? Y0 - P.halo_t : 0) >> L;
@@ -170,6 +207,10 @@ struct InvWave {
     ks.base = -1;
 
     if (kbeg >= kend) return;
+    prefetch<1>(k0[1]);
+    if constexpr (L >= 2) prefetch<2>(k0[2]);
+    if constexpr (L >= 3) prefetch<3>(k0[3]);
+    if constexpr (L >= 4) prefetch<4>(k0[4]);
     constexpr int U = C<L> / 2;
     int nxt[U];
     load_ll(kbeg, nxt);
@@ -191,10 +232,9 @@ struct InvWave {
 };
 
 template <int L, int C1, bool U8OUT>
-__global__ __launch_bounds__(kBlockThreads) void inv_kernel(const int16_t *__restrict__ llin,
-                                                            const int16_t *__restrict__ pub,
-                                                            void *__restrict__ out,
-                                                            const StageParams P) {
+__device__ __forceinline__ void inv_body(const int16_t *__restrict__ llin,
+                                         const int16_t *__restrict__ pub, void *__restrict__ out,
+                                         const StageParams &P) {
   __shared__ uint32_t s_te[1024];
   __shared__ uint32_t s_kw[kKeyWords];
   __shared__ uint32_t s_ring[kWavesPerBlock][kRingBlocks * 4];
@@ -219,13 +259,138 @@ __global__ __launch_bounds__(kBlockThreads) void inv_kernel(const int16_t *__res
   w.run(wave);
 }
 
+// Eight columns per lane: held to 128 VGPRs (four wavefronts per SIMD), the
+// occupancy that hides the detail-row loads.
+template <int L, bool U8OUT>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void inv_kernel8(const int16_t *__restrict__ llin, const int16_t *__restrict__ pub,
+                 void *__restrict__ out, const StageParams P) {
+  inv_body<L, 8, U8OUT>(llin, pub, out, P);
+}
+
+// Sixteen columns per lane need more registers than that.
+template <int L, bool U8OUT>
+__global__ __launch_bounds__(kBlockThreads) void inv_kernel16(const int16_t *__restrict__ llin,
+                                                             const int16_t *__restrict__ pub,
+                                                             void *__restrict__ out,
+                                                             const StageParams P) {
+  inv_body<L, 16, U8OUT>(llin, pub, out, P);
+}
+
+template <int L, int C1, bool U8OUT>
+static const void *inv_fn() {
+  if constexpr (C1 == 8) return reinterpret_cast<const void *>(&inv_kernel8<L, U8OUT>);
+  else return reinterpret_cast<const void *>(&inv_kernel16<L, U8OUT>);
+}
+
 template <int L, int C1, bool U8OUT>
 static hipError_t launch_inv_t(const int16_t *llin, const int16_t *pub, void *out,
                                const StageParams &P, hipStream_t s) {
   const int blocks = (P.n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
-  hipLaunchKernelGGL((inv_kernel<L, C1, U8OUT>), dim3(blocks), dim3(kBlockThreads), 0, s, llin,
-                     pub, out, P);
+  if constexpr (C1 == 8)
+    hipLaunchKernelGGL((inv_kernel8<L, U8OUT>), dim3(blocks), dim3(kBlockThreads), 0, s, llin, pub,
+                       out, P);
+  else
+    hipLaunchKernelGGL((inv_kernel16<L, U8OUT>), dim3(blocks), dim3(kBlockThreads), 0, s, llin,
+                       pub, out, P);
   return hipGetLastError();
+}
+
+// Batch form: a persistent launch drains one class's tile queue.  Items carry
+// their own keys: each wavefront stages its tile's round keys and nonce in
+// its own LDS slot.
+template <int L, int C1>
+__device__ __forceinline__ void inv_batch_body(const BatchItem *__restrict__ items,
+                                               const int2 *__restrict__ tiles, int64_t n_tiles,
+                                               unsigned int *__restrict__ head) {
+  __shared__ uint32_t s_te[1024];
+  __shared__ uint32_t s_kw[kWavesPerBlock][kKeyWords];
+  __shared__ uint32_t s_ring[kWavesPerBlock][kRingBlocks * 4];
+  for (int i = threadIdx.x; i < 1024; i += blockDim.x) {
+    const uint32_t v = c_aes.te0[i & 255];
+    const int r = 8 * (i >> 8);
+    s_te[i] = r ? ((v << r) | (v >> (32 - r))) : v;
+  }
+  __syncthreads();
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    unsigned int t = 0;
+    if (lane == 0) t = atomicAdd(head, 1u);
+    t = __builtin_amdgcn_readfirstlane(t);
+    if (int64_t(t) >= n_tiles) break;
+    const int2 e = tiles[t];
+    const BatchItem &it = items[e.x];
+    if (lane < kKeyWords) {
+      const AesKey &k = it.inv.key;
+      uint32_t v;
+      if (lane < 44) v = k.rk[lane];
+      else if (lane == 44) v = uint32_t(k.nonce_hi);
+      else if (lane == 45) v = uint32_t(k.nonce_hi >> 32);
+      else if (lane == 46) v = uint32_t(k.nonce_lo);
+      else v = uint32_t(k.nonce_lo >> 32);
+      s_kw[wib][lane] = v;
+    }
+    wave_lds_sync();
+    InvWave<L, C1, true> w{it.inv};
+    w.llin = reinterpret_cast<const int16_t *>(it.priv);
+    w.pub = it.pub;
+    w.out8 = it.out;
+    w.out16 = nullptr;
+    w.lane = lane;
+    w.ks.ring = s_ring[wib];
+    w.ks.te = s_te;
+    w.ks.kw = s_kw[wib];
+    w.ks.rows = it.inv.ks_rows;
+    w.ks.blocks = it.inv.ks_blocks;
+    w.run(e.y);
+    wave_lds_sync();
+  }
+}
+
+template <int L>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void inv_batch_kernel8(const BatchItem *__restrict__ items, const int2 *__restrict__ tiles,
+                       int64_t n_tiles, unsigned int *__restrict__ head) {
+  inv_batch_body<L, 8>(items, tiles, n_tiles, head);
+}
+
+template <int L>
+__global__ __launch_bounds__(kBlockThreads) void inv_batch_kernel16(const BatchItem *__restrict__ items,
+                                                                   const int2 *__restrict__ tiles,
+                                                                   int64_t n_tiles,
+                                                                   unsigned int *__restrict__ head) {
+  inv_batch_body<L, 16>(items, tiles, n_tiles, head);
+}
+
+hipError_t launch_inv_batch(int L, int C1, const BatchItem *items, const int2 *tiles, int64_t n_tiles,
+                            unsigned int *head, int blocks, hipStream_t s) {
+#define DWTFRAG_CASE(LL, CC, K)                                                              \
+  if (L == LL && C1 == CC) {                                                                 \
+    hipLaunchKernelGGL((K<LL>), dim3(blocks), dim3(kBlockThreads), 0, s, items, tiles,       \
+                       n_tiles, head);                                                       \
+    return hipGetLastError();                                                                \
+  }
+  DWTFRAG_CASE(1, 8, inv_batch_kernel8) DWTFRAG_CASE(2, 8, inv_batch_kernel8)
+  DWTFRAG_CASE(3, 8, inv_batch_kernel8) DWTFRAG_CASE(1, 16, inv_batch_kernel16)
+  DWTFRAG_CASE(2, 16, inv_batch_kernel16) DWTFRAG_CASE(3, 16, inv_batch_kernel16)
+  DWTFRAG_CASE(4, 16, inv_batch_kernel16)
+#undef DWTFRAG_CASE
+  return hipErrorInvalidValue;
+}
+
+// Resident wavefronts per CU of the inverse kernel for (L, C1).
+int inv_waves_per_cu(int L, int C1, bool u8out) {
+  const void *fn = nullptr;
+#define DWTFRAG_FN(LL, CC) \
+  if (L == LL && C1 == CC) fn = u8out ? inv_fn<LL, CC, true>() : inv_fn<LL, CC, false>();
+  DWTFRAG_FN(1, 8) DWTFRAG_FN(2, 8) DWTFRAG_FN(3, 8)
+  DWTFRAG_FN(1, 16) DWTFRAG_FN(2, 16) DWTFRAG_FN(3, 16) DWTFRAG_FN(4, 16)
+#undef DWTFRAG_FN
+  int blocks = 0;
+  if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kBlockThreads, 0) != hipSuccess)
+    return 0;
+  return blocks * kWavesPerBlock;
 }
 
 hipError_t launch_inv(int L, int C1, bool u8out, const int16_t *llin, const int16_t *pub,

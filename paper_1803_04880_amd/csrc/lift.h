@@ -77,12 +77,13 @@ __device__ __forceinline__ void hinv_any(int (&v)[C], int j0, int N, bool edge) 
 }
 
 // ------------------------------------------------------- int16 row I/O --
-// U consecutive int16 band values starting at element index idx.  `nvalid`
-// (0..U) of them exist; vector access when all exist and idx is U-aligned.
+// U consecutive int16 band values starting at element index idx.  The first
+// `nvalid` of them exist (nvalid may exceed U); vector access when all U exist
+// and idx is U-aligned.
 template <int U>
 __device__ __forceinline__ void store_i16(int16_t *base, int64_t idx, int nvalid, const int (&v)[U]) {
   if (nvalid <= 0) return;
-  if (U >= 2 && nvalid == U && (idx & (U - 1)) == 0) {
+  if (U >= 2 && nvalid >= U && (idx & (U - 1)) == 0) {
     uint32_t w[U / 2 > 0 ? U / 2 : 1];
 #pragma unroll
     for (int i = 0; i < U / 2; ++i)
@@ -108,7 +109,7 @@ __device__ __forceinline__ void store_i16(int16_t *base, int64_t idx, int nvalid
 
 template <int U>
 __device__ __forceinline__ void load_i16(const int16_t *base, int64_t idx, int nvalid, int (&v)[U]) {
-  if (U >= 2 && nvalid == U && (idx & (U - 1)) == 0) {
+  if (U >= 2 && nvalid >= U && (idx & (U - 1)) == 0) {
     uint32_t w[U / 2 > 0 ? U / 2 : 1];
     if constexpr (U == 2) {
       w[0] = *reinterpret_cast<const uint32_t *>(base + idx);
@@ -134,6 +135,42 @@ __device__ __forceinline__ void load_i16(const int16_t *base, int64_t idx, int n
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) v[u] = (u < nvalid) ? int(base[idx + u]) : 0;
+}
+
+// Raw form: U int16 values as W = max(1, U/2) packed words (value u in the
+// low / high half of word u/2), for rows loaded ahead of their use.
+template <int U> struct Raw { static constexpr int W = U >= 2 ? U / 2 : 1; };
+
+template <int U>
+__device__ __forceinline__ void load_raw(const int16_t *base, int64_t idx, int nvalid,
+                                         uint32_t (&w)[Raw<U>::W]) {
+  if (U >= 2 && nvalid >= U && (idx & (U - 1)) == 0) {
+    if constexpr (U == 2) {
+      w[0] = *reinterpret_cast<const uint32_t *>(base + idx);
+    } else if constexpr (U == 4) {
+      const uint2 q = *reinterpret_cast<const uint2 *>(base + idx);
+      w[0] = q.x; w[1] = q.y;
+    } else {
+#pragma unroll
+      for (int i = 0; i < U / 8; ++i) {
+        const uint4 q = reinterpret_cast<const uint4 *>(base + idx)[i];
+        w[4 * i] = q.x; w[4 * i + 1] = q.y; w[4 * i + 2] = q.z; w[4 * i + 3] = q.w;
+      }
+    }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < Raw<U>::W; ++i) w[i] = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (u < nvalid) w[u >> 1] |= uint32_t(uint16_t(base[idx + u])) << (16 * (u & 1));
+}
+
+template <int U>
+__device__ __forceinline__ void unpack_raw(const uint32_t (&w)[Raw<U>::W], int (&v)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    v[u] = (u & 1) ? int(int32_t(w[u >> 1]) >> 16) : int(int16_t(uint16_t(w[u >> 1] & 0xFFFFu)));
 }
 
 // ------------------------------------------------------ keystream ring --

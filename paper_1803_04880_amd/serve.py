@@ -1,0 +1,154 @@
+"""Serving loop: continuous batching of protect / restore requests on one GPU.
+
+Requests arrive over time (each names a device-resident buffer, or a pair of
+fragments to restore).  The loop admits every arrived request that fits the
+device-memory budget, plans the admitted protect requests and the admitted
+restore requests as two batches (``batch.Batch``: persistent tile-queue
+launches over uneven buffers), launches them on one of two streams, and
+retires a batch when its completion event has fired, releasing its memory.
+While one batch runs on the GPU the host plans and launches the next one on
+the other stream, so planning overlaps device work.  Every request's result
+is exactly what a lone ``protect`` / ``restore`` call gives (the batch path
+computes each item independently).
+
+The per-request latency is arrival -> completion as seen by the host (the
+event's completion is polled; the clock is ``time.perf_counter``).
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from collections import deque
+
+import torch
+
+from . import geometry
+from .batch import Batch
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    op: str                      # "protect" or "restore"
+    arrival: float               # seconds from the start of the run
+    n: int
+    width: int
+    levels: int
+    key: bytes
+    nonce: bytes
+    x: torch.Tensor | None = None      # protect input (device)
+    priv: torch.Tensor | None = None   # restore inputs (device)
+    pub: torch.Tensor | None = None
+    # results
+    out_priv: torch.Tensor | None = None
+    out_pub: torch.Tensor | None = None
+    out: torch.Tensor | None = None
+    done: float | None = None
+
+    def device_bytes(self) -> int:
+        g = geometry(self.n, self.width, self.levels)
+        return g["priv_bytes"] + g["pub_bytes"] if self.op == "protect" else self.n
+
+
+@dataclasses.dataclass
+class _InFlight:
+    reqs: list
+    event: torch.cuda.Event
+    bytes: int
+    batches: list
+
+
+class Server:
+    """Continuous-batching executor.  ``budget_bytes`` bounds the device
+    memory of results in flight (outputs of admitted, unfinished requests);
+    ``max_batch`` bounds the requests per launch."""
+
+    def __init__(self, budget_bytes: int = 64 << 30, max_batch: int = 512, device="cuda:0"):
+        self.budget = budget_bytes
+        self.max_batch = max_batch
+        self.device = torch.device(device)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(2)]
+        self.turn = 0
+        self.in_use = 0
+        self.inflight: deque[_InFlight] = deque()
+        self.batches_launched = 0
+        self.on_complete = None   # called with each request when its batch has finished
+
+    def _launch(self, reqs):
+        prot = [r for r in reqs if r.op == "protect"]
+        rest = [r for r in reqs if r.op == "restore"]
+        stream = self.streams[self.turn]
+        self.turn ^= 1
+        used = sum(r.device_bytes() for r in reqs)
+        batches = []
+        with torch.cuda.stream(stream):
+            if prot:
+                b = Batch([r.x for r in prot], [r.width for r in prot], [r.levels for r in prot],
+                          [r.key for r in prot], [r.nonce for r in prot],
+                          outs=[r.x for r in prot])   # protect never writes `out`
+                b.protect(stream=stream)
+                for r, p, q in zip(prot, b.privs, b.pubs):
+                    r.out_priv, r.out_pub = p, q
+                batches.append(b)
+            if rest:
+                outs = [torch.empty(r.n, dtype=torch.uint8, device=self.device) for r in rest]
+                # restore reads only the fragments: the outputs stand in as inputs
+                b = Batch(outs, [r.width for r in rest], [r.levels for r in rest],
+                          [r.key for r in rest], [r.nonce for r in rest],
+                          privs=[r.priv for r in rest], pubs=[r.pub for r in rest], outs=outs)
+                b.restore(stream=stream)
+                for r, o in zip(rest, outs):
+                    r.out = o
+                batches.append(b)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        self.in_use += used
+        self.inflight.append(_InFlight(reqs, ev, used, batches))
+        self.batches_launched += 1
+
+    def _retire(self, now_fn, block=False):
+        while self.inflight:
+            f = self.inflight[0]
+            if block:
+                f.event.synchronize()
+            elif not f.event.query():
+                return
+            t = now_fn()
+            for r in f.reqs:
+                r.done = t
+                if self.on_complete is not None:
+                    self.on_complete(r)
+            for b in f.batches:
+                b.close()
+            self.in_use -= f.bytes
+            self.inflight.popleft()
+
+    def run(self, requests, time_scale: float = 1.0):
+        """Serve ``requests`` (sorted by arrival) in real time; returns the
+        wall time of the run.  ``time_scale`` stretches arrival times."""
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0  # noqa: E731
+        waiting: deque[Request] = deque()
+        while pending or waiting or self.inflight:
+            t = now()
+            while pending and pending[0].arrival * time_scale <= t:
+                waiting.append(pending.popleft())
+            self._retire(now)
+            take, room = [], self.budget - self.in_use
+            while waiting and len(take) < self.max_batch:
+                need = waiting[0].device_bytes()
+                if need > room and (take or self.inflight):
+                    break
+                room -= need
+                take.append(waiting.popleft())
+            if take and len(self.inflight) < 2:
+                self._launch(take)
+            elif take:
+                for r in reversed(take):   # both streams busy: keep them queued
+                    waiting.appendleft(r)
+                self._retire(now, block=True)
+            elif not waiting and pending and not self.inflight:
+                time.sleep(max(0.0, min(pending[0].arrival * time_scale - now(), 0.001)))
+        self._retire(now, block=True)
+        return now()

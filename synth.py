@@ -131,6 +131,20 @@ def config_large():
                 levels=3, key=key, nonce=nonce)
 
 
+LEARNED_IMAGES = 64
+
+
+def learned_image(i: int) -> np.ndarray:
+    """Image i of the learned-predictor workload: a 4096 x 4096 smooth field
+    (seed 4000 + i), as a flat byte buffer."""
+    return smooth(4096, 4096, 4000 + i).reshape(-1)
+
+
+def learned_key_nonce(i: int) -> tuple[bytes, bytes]:
+    """Key (shared) and per-image nonce of the learned-predictor workload."""
+    return np.random.default_rng(104).bytes(16), np.random.default_rng(5000 + i).bytes(16)
+
+
 def default_width(n: int) -> int:
     """min(4096, next power of two >= ceil(sqrt(n)))."""
     r = math.isqrt(n)

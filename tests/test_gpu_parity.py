@@ -170,3 +170,24 @@ def test_large_workload_digest_and_roundtrip():
                            cfg["nonce"])
     torch.cuda.synchronize()
     assert torch.equal(back, x)
+
+
+@pytest.mark.parametrize("n,width,levels,launch", [
+    (1000 * 37 + 5, 1000, 1, None), (268568, 1024, 1, None), (31683, 256, 2, (0, 16)),
+    (4097, 64, 3, None), (100003, 317, 3, (16, 8)), (70000, 4096, 4, None), (5000, 71, 5, None),
+])
+def test_restore_writes_nothing_past_n(n, width, levels, launch):
+    """The last row of the view is partial: restore writes exactly n bytes
+    (a guard region right after the output keeps its pattern)."""
+    rng = np.random.default_rng(n + levels)
+    buf = rng.integers(0, 256, n, dtype=np.uint8)
+    key, nonce = rng.bytes(16), rng.bytes(16)
+    _say(f"guard n={n} width={width} levels={levels} launch={launch}")
+    x = torch.from_numpy(buf).to(DEV)
+    priv, pub = dwtfrag.protect(x, width, levels, key, nonce, launch=launch)
+    guard = 16384
+    big = torch.full((n + guard,), 0xA5, dtype=torch.uint8, device=DEV)
+    dwtfrag.restore(priv, pub, n, width, levels, key, nonce, out=big[:n], launch=launch)
+    torch.cuda.synchronize()
+    assert torch.equal(big[:n], x)
+    assert bool((big[n:] == 0xA5).all()), "restore wrote past n"

@@ -237,3 +237,17 @@ def test_training_lowers_loss_and_entropy():
     _, det = L.fwd_multilevel(img, 2, net)
     _, det0 = dwt53.fwd_multilevel(img, 2)
     assert L.detail_entropy(det) < L.detail_entropy(det0)
+
+
+def test_fragments_zero_network_and_roundtrip():
+    """Learned fragments with the zero network are the plain fragments; with
+    any network restore inverts protect."""
+    from oracle import fragment
+    rng = np.random.default_rng(15)
+    buf = rng.integers(0, 256, 5000).astype(np.uint8)
+    key, nonce = rng.bytes(16), rng.bytes(16)
+    assert L.protect(buf, 77, 3, key, nonce, L.Predictor.zero()) == \
+        fragment.protect(buf, 77, 3, key, nonce)
+    net = rand_net(rng)
+    priv, pub = L.protect(buf, 77, 3, key, nonce, net)
+    assert L.restore(priv, pub, 5000, 77, 3, key, nonce, net) == buf.tobytes()
