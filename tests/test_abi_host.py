@@ -116,3 +116,46 @@ def test_product_path_has_no_oracle_dependency():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in re.sub(r"#.*|//.*", "", text), f
+
+
+def _item(n, width, levels, base=1 << 20):
+    from paper_1803_04880_amd.batch import Item
+    it = Item()
+    it.in_, it.out, it.priv, it.pub = base, base + (1 << 30), base + (2 << 30), base + (3 << 30)
+    it.n, it.width, it.levels = n, width, levels
+    return it
+
+
+def test_batch_planner_host_logic():
+    """Planning is host work: valid items give a plan and its device size;
+    bad items are rejected before anything touches a device."""
+    L = _lib_or_skip()
+    from paper_1803_04880_amd.batch import Item
+    items = (Item * 3)(_item(1000, 32, 1), _item(70000, 256, 4), _item(5, 2, 2))
+    h = ctypes.c_void_p()
+    assert L.dwtfrag_batch_create(ctypes.addressof(items), 3, None, 0, ctypes.byref(h)) == 0
+    assert L.dwtfrag_batch_device_bytes(h) >= 256
+    assert L.dwtfrag_batch_protect(h, None) == pkg.DWTFRAG_EINVAL   # not uploaded
+    L.dwtfrag_batch_destroy(h)
+    for bad in (_item(100, 10, 5), _item(100, 10, 0), _item(100, 0, 1), _item(100, 10, 1, base=8)):
+        one = (Item * 1)(bad)
+        h = ctypes.c_void_p()
+        rc = L.dwtfrag_batch_create(ctypes.addressof(one), 1, None, 0, ctypes.byref(h))
+        assert rc == pkg.DWTFRAG_EINVAL and not h.value
+    assert L.dwtfrag_batch_create(None, 1, None, 0, ctypes.byref(h)) == pkg.DWTFRAG_EINVAL
+
+
+def test_learned_geometry_pairs_and_limits():
+    from oracle import learned
+    import numpy as np
+    from paper_1803_04880_amd import learned as GL
+    _lib_or_skip()
+    for n, w, lv in ((1, 1, 1), (1000, 1, 3), (12345, 97, 2), (4096 * 4096, 4096, 3)):
+        _, pairs = GL.learned_geometry(n, w, lv)
+        h = -(-n // w)
+        if n <= 20000:
+            ctx, t = learned.training_pairs(np.zeros((h, w), np.int64), lv)
+            assert pairs == t.size
+        assert pairs > 0 or (h == 1 and w == 1)
+    with pytest.raises(pkg.DwtfragError):
+        GL.learned_geometry(100, 10, 4)
