@@ -80,10 +80,16 @@ def cpu_baseline(cfg, rows: int = 2048, row0: int = 2048):
     back = fragment.restore(priv, pub, sample.size, w, lv, cfg["key"], cfg["nonce"])
     dt = time.perf_counter() - t0
     assert back == sample.tobytes()
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return dict(value=round(sample.size / dt / 1e9, 4), unit="GB/s", cores=1, kind="oracle",
                 sample=f"rows {row0}..{row0 + rows} of the {w}-wide workload "
                        f"({sample.size / 2**20:.0f} MiB, {lv} levels), protect+restore, "
-                       f"NumPy oracle in one process, {dt:.1f} s")
+                       f"NumPy oracle in one process on {cpu}, {dt:.1f} s")
 
 
 def main():
@@ -91,7 +97,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", choices=["large", "small", "learned", "serve"], default="large")
+    ap.add_argument("--config", choices=["large", "small", "learned", "serve", "batch"], default="large")
+    ap.add_argument("--count", type=int, default=2048, help="batch config: number of buffers")
     ap.add_argument("--duration", type=float, default=30.0, help="serve config: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve config: arrivals per second")
     ap.add_argument("--images", type=int, default=0,
@@ -122,6 +129,8 @@ def main():
         return run_learned(args)
     if args.config == "serve":
         return run_serve(args)
+    if args.config == "batch":
+        return run_batch(args)
 
     import numpy as np
     import torch
@@ -241,7 +250,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32",
+        "dtype": "int16/int32",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "n_bytes": n, "rows": H, "width": width,
                    "levels": levels, "launch": {"seg_rows": args.seg_rows, "lane_cols": args.lane_cols}},
@@ -260,6 +269,80 @@ def main():
     if not args.no_cpu_baseline and args.config == "large":
         log("timing the CPU oracle on a bounded sample ...")
         result["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(result), flush=True)
+
+
+def run_batch(args):
+    """Uneven batch: --count buffers (default 2048), sizes floor(exp U(ln 2^12,
+    ln 2^26)) and levels U{1..4} from the seeded specs of synth.batch_specs,
+    default widths; contents random bytes from a seeded device generator.
+    Launch shapes are autotuned per (width, levels) class before timing; a
+    step is one batched protect + one batched restore of every buffer."""
+    import torch
+
+    import synth
+    from paper_1803_04880_amd import batch as B
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    specs = synth.batch_specs(args.count)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(3)
+    xs = [torch.randint(0, 256, (s["n"],), dtype=torch.uint8, device=dev, generator=gen)
+          for s in specs]
+    total = sum(s["n"] for s in specs)
+    log(f"{len(specs)} buffers, {total / 1e9:.2f} GB")
+    t0 = time.time()
+    tune = {}
+    for s, x in zip(specs, xs):
+        key = (s["width"], s["levels"])
+        if key not in tune:
+            tune[key] = B.autotune(x, s["width"], s["levels"], trials=2)[0]
+    log(f"autotuned {len(tune)} classes in {time.time() - t0:.1f}s")
+    b = B.Batch(xs, [s["width"] for s in specs], [s["levels"] for s in specs],
+                [bytes(16)] * len(specs), [s["nonce"] for s in specs], tune=tune)
+    b.protect()
+    b.restore()
+    torch.cuda.synchronize()
+    ok = all(bool(torch.equal(o, x)) for o, x in zip(b.outs, xs))
+    stream = torch.cuda.current_stream()
+    steps = args.steps if args.steps != 50 else 5
+    warmup = args.warmup if args.warmup != 5 else 1
+    for _ in range(warmup):
+        b.protect()
+        b.restore()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    w0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        b.protect()
+        ev[k][1].record(stream)
+        b.restore()
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    tp = [ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]
+    tr = [ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]
+    alg = 3 * total + 3 * total   # about 3 B per element each way
+    pair_ms = (sum(tp) + sum(tr)) / steps
+    result = {
+        "metric": "batched protect+restore GB/s on 1 MI355X, bit-exact",
+        "value": round(total * steps / wall / 1e9, 2), "unit": "GB/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": round(wall / steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int16/int32", "data": "synthetic",
+        "config": {"workload": f"{len(specs)} uneven buffers ({total / 1e9:.2f} GB), 1-4 levels, "
+                               "autotuned tile shape per (width, levels) class",
+                   "buffers": len(specs), "bytes": total, "classes": len(tune)},
+        "bit_exact_roundtrip": ok,
+        "latency_ms": {"protect_p50": round(percentile(tp, 50), 3),
+                       "restore_p50": round(percentile(tr, 50), 3)},
+        "roofline": {"bound": "hbm", "achieved": round(alg / (pair_ms * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(alg / (pair_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "all batch launches of protect+restore"},
+        "cpu_baseline": None,
+    }
     print(json.dumps(result), flush=True)
 
 
@@ -395,13 +478,15 @@ def run_learned(args):
         for i in range(nimg):
             GL.restore(privs[i], pubs[i], n, W, L, kn[i][0], kn[i][1], net, out=outs[i], ws=ws)
 
+    from paper_1803_04880_amd import batch as B
+    plain = B.Batch(xs, [W] * nimg, [L] * nimg, [k for k, _ in kn], [v for _, v in kn],
+                    privs=privs, pubs=pubs, outs=outs)
+
     def plain_protect_all():
-        for i in range(nimg):
-            dwtfrag.protect(xs[i], W, L, kn[i][0], kn[i][1], priv=privs[i], pub=pubs[i])
+        plain.protect()
 
     def plain_restore_all():
-        for i in range(nimg):
-            dwtfrag.restore(privs[i], pubs[i], n, W, L, kn[i][0], kn[i][1], out=outs[i])
+        plain.restore()
 
     # parity: image 0 against the oracle's digest, every image round trips
     protect_all(gold_net)
@@ -489,7 +574,7 @@ def run_learned(args):
         "bit_exact": bool(bit_exact),
         "latency_us": {"protect_all_p50": round(percentile(tp, 50), 1),
                        "restore_all_p50": round(percentile(tr, 50), 1)},
-        "plain_53": {"value": round(total * steps / wall_p / 1e9, 2), "unit": "GB/s",
+        "plain_53_batched": {"value": round(total * steps / wall_p / 1e9, 2), "unit": "GB/s",
                      "protect_all_p50_us": round(percentile(tp_p, 50), 1),
                      "restore_all_p50_us": round(percentile(tr_p, 50), 1)},
         "entropy_bits": {"plain_53": round(ent_plain, 4), "learned_oracle_net": round(ent_learned, 4),

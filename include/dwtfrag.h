@@ -75,9 +75,12 @@ typedef struct {
 } dwtfrag_geom;
 
 /* Optional launch shape (0 in a field = library default).  Results do not
- * depend on it; it only trades parallelism against halo recomputation. */
+ * depend on it; it only trades parallelism against halo recomputation.  The
+ * default cuts the rows into as many segments as the device keeps wavefronts
+ * resident for that kernel (one round), at least two 2^levels-row units each. */
 typedef struct {
-  uint32_t seg_rows;        /* rows owned by one wavefront (rounded up to 2^levels) */
+  uint32_t seg_rows;        /* rows per segment (rounded up to 2^levels; segments are
+                               balanced to within 2^levels rows) */
   uint32_t lane_cols;       /* columns per lane at level 1: 8 or 16 (16 needed for 4 levels) */
 } dwtfrag_launch;
 
