@@ -99,6 +99,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", choices=["large", "small", "learned", "serve", "batch"], default="large")
     ap.add_argument("--count", type=int, default=2048, help="batch config: number of buffers")
+    ap.add_argument("--no-tune", action="store_true", help="batch config: default tile shapes")
     ap.add_argument("--duration", type=float, default=30.0, help="serve config: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve config: arrivals per second")
     ap.add_argument("--images", type=int, default=0,
@@ -294,11 +295,10 @@ def run_batch(args):
     log(f"{len(specs)} buffers, {total / 1e9:.2f} GB")
     t0 = time.time()
     tune = {}
-    for s, x in zip(specs, xs):
-        key = (s["width"], s["levels"])
-        if key not in tune:
-            tune[key] = B.autotune(x, s["width"], s["levels"], trials=2)[0]
-    log(f"autotuned {len(tune)} classes in {time.time() - t0:.1f}s")
+    if not args.no_tune:
+        tune = B.tune_classes(xs, [s["width"] for s in specs], [s["levels"] for s in specs])
+        log(f"tuned {len(tune)} classes in {time.time() - t0:.1f}s: "
+            + ", ".join(f"{k}->({v.seg_rows},{v.lane_cols})" for k, v in sorted(tune.items())))
     b = B.Batch(xs, [s["width"] for s in specs], [s["levels"] for s in specs],
                 [bytes(16)] * len(specs), [s["nonce"] for s in specs], tune=tune)
     b.protect()
@@ -332,7 +332,8 @@ def run_batch(args):
         "warmup": warmup, "ms_per_step": round(wall / steps * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int16/int32", "data": "synthetic",
         "config": {"workload": f"{len(specs)} uneven buffers ({total / 1e9:.2f} GB), 1-4 levels, "
-                               "autotuned tile shape per (width, levels) class",
+                               + ("default tile shapes" if args.no_tune else
+                                  "tile shape per (width, levels) class tuned on batched runs"),
                    "buffers": len(specs), "bytes": total, "classes": len(tune)},
         "bit_exact_roundtrip": ok,
         "latency_ms": {"protect_p50": round(percentile(tp, 50), 3),

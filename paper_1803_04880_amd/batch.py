@@ -45,6 +45,47 @@ def autotune(x: torch.Tensor, width: int, levels: int, trials: int = 3, stream=N
     return best, float(us.value)
 
 
+def tune_classes(buffers, widths, levels, trials: int = 2,
+                 candidates=((64, 8), (128, 8), (256, 8), (128, 16), (256, 16)), stream=None):
+    """Batch autotuner: for every (width, levels) class of the buffers, time a
+    batched protect + restore of that class's buffers under each candidate
+    tile shape (rows per tile, columns per lane) with HIP events and keep the
+    fastest.  Returns {(width, levels): Launch} for ``Batch(tune=...)``.
+
+    Unlike ``autotune`` (one buffer alone, where finer tiles fill the device),
+    this times the shapes where they will run: many buffers per launch, where
+    coarser tiles save halo work."""
+    groups = {}
+    for i, (w, lv) in enumerate(zip(widths, levels)):
+        groups.setdefault((w, lv), []).append(i)
+    st = torch.cuda.current_stream() if stream is None else stream
+    result = {}
+    for key, idx in groups.items():
+        xs = [buffers[i] for i in idx]
+        best = None
+        for rows, cols in candidates:
+            if key[1] % 4 == 0 and cols == 8:
+                continue   # a four-level stage needs 16 columns per lane
+            b = Batch(xs, [key[0]] * len(xs), [key[1]] * len(xs), [bytes(16)] * len(xs),
+                      [bytes(16)] * len(xs), tune={key: (rows, cols)})
+            b.protect(stream=st)
+            b.restore(stream=st)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(trials):
+                b.protect(stream=st)
+                b.restore(stream=st)
+            e1.record(st)
+            e1.synchronize()
+            t = e0.elapsed_time(e1) / trials
+            if best is None or t < best[0]:
+                best = (t, rows, cols)
+            b.close()
+            del b
+        result[key] = Launch(best[1], best[2])
+    return result
+
+
 class Batch:
     """A planned batch; owns the fragment and output tensors unless given."""
 

@@ -185,3 +185,21 @@ def test_serving_loop_results_equal_lone_calls():
             assert torch.equal(r.out_priv, p) and torch.equal(r.out_pub, q), f"request {r.rid}"
         else:
             assert torch.equal(r.out, x), f"request {r.rid}"
+
+
+def test_batch_class_tuner_and_tuned_batch():
+    specs = _specs(30, 13, lo=5000, hi=300000)
+    xs = [torch.from_numpy(s["buf"]).to(DEV) for s in specs]
+    tune = B.tune_classes(xs, [s["width"] for s in specs], [s["levels"] for s in specs], trials=1)
+    assert set(tune) == {(s["width"], s["levels"]) for s in specs}
+    for (w, lv), ln in tune.items():
+        assert ln.lane_cols in (8, 16) and ln.seg_rows in (64, 128, 256)
+        assert lv < 4 or ln.lane_cols == 16
+    _say(f"class tuner: {len(tune)} classes")
+    b = _make_batch(specs, tune=tune)
+    b.protect()
+    b.restore()
+    torch.cuda.synchronize()
+    _check_against_oracle(b, specs)
+    for i, s in enumerate(specs):
+        assert b.outs[i].cpu().numpy().tobytes() == s["buf"].tobytes()
