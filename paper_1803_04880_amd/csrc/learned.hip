@@ -12,9 +12,11 @@
 //   d(i) = x(i) - base - corr
 // The context reads even samples only, which the inverse rebuilds first.
 //
-// Layout of the work: the network costs ~100 VALU operations per predicted
-// sample (the plain predict costs ~2), so this path is ALU-bound and each 1-D
-// pass runs as its own kernel over int32 intermediates in HBM.  A block
+// Layout of the work: the network's hidden layer runs on the matrix cores
+// (int8 MFMA, see correction_mfma), its output layer and the context on the
+// VALU; that is still ~60 operations per predicted sample against ~2 for the
+// plain predict, so this path is ALU-bound and each 1-D pass runs as its own
+// kernel over int32 intermediates in HBM.  A block
 // takes SEG positions of LINES independent lines (rows: 1 line of 2048
 // positions; columns: 64 lines of 64 positions), loads them with an 8-sample
 // halo on each side, mirrored at the signal edges, into LDS as separate even
@@ -81,22 +83,70 @@ __device__ __forceinline__ int hidden_pre(const uint32_t (&w1)[2], int b1, uint3
   return __builtin_amdgcn_sdot4(int(hi), int(w1[1]), p, false);
 }
 
-// corr of the eight even neighbours e[0..7] (positions i-7, i-5, ..., i+7)
-// around base.  h < 2^18 under the parameter limits the entry points check,
-// so the clamp to 2^23 - 1 is a no-op that lets W2 h run as a 24-bit multiply.
-__device__ __forceinline__ int correction(const Net &net, const int (&e)[kCtx], int base) {
+// corr of 64 contexts at once, one per lane of a wavefront (context of lane
+// l = sample l), on the matrix cores.  The hidden layer is
+// D = A_g x B + bias with v_mfma_i32_16x16x32_i8: B (32 x 16) holds, in
+// k-group g = l / 16 and column l % 16, the eight context bytes of lane l;
+// A_g (16 x 32) holds W1 in k-group g and zeros elsewhere, so D_g's column j
+// is the 16 hidden pre-activations of sample 16 g + j.  Lane l receives rows
+// 4 (l / 16) .. +3 of column l % 16; ReLU, the W2 products and a sum over
+// the four 16-lane rows give the output of sample 16 g + l % 16, which lane
+// 16 g + l % 16 keeps.  Every step is exact integer arithmetic; h < 2^18
+// under the parameter limits the entry points check, so the clamp to
+// 2^23 - 1 is a no-op that lets W2 h run as a 24-bit multiply.  All 64 lanes
+// must call it together.
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+struct MfmaNet {
+  long a[4];   // A_g operand of this lane: W1 row (l % 16) in k-group l / 16 == g
+  v4i bias;    // b1 of hidden rows 4 (l / 16) + r
+  int w2[4];   // W2 of the same rows
+  int b2, shift;
+};
+
+// Net staged in LDS as words: w1 (32), b1 (16), w2 (16).
+__device__ __forceinline__ MfmaNet mfma_net(const uint32_t *s_net, int b2, int shift, int lane) {
+  MfmaNet m;
+  const int h = lane & 15, g0 = lane >> 4;
+  const long w = long(s_net[2 * h]) | (long(s_net[2 * h + 1]) << 32);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) m.a[g] = (g == g0) ? w : 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    m.bias[r] = int(s_net[32 + 4 * g0 + r]);
+    m.w2[r] = (int(s_net[48 + 4 * g0 + r]) << 24) >> 24;
+  }
+  m.b2 = b2;
+  m.shift = shift;
+  return m;
+}
+
+__device__ __forceinline__ int correction_mfma(const MfmaNet &m, const int (&e)[kCtx], int base,
+                                               int lane) {
   int c[kCtx];
 #pragma unroll
   for (int j = 0; j < kCtx; ++j) c[j] = clamp_i(e[j] - base, -128, 127);
-  const uint32_t lo = pack4(c[0], c[1], c[2], c[3]);
-  const uint32_t hi = pack4(c[4], c[5], c[6], c[7]);
-  int acc = net.b2;
+  const long b = long(pack4(c[0], c[1], c[2], c[3])) | (long(pack4(c[4], c[5], c[6], c[7])) << 32);
+  int mine = 0;
 #pragma unroll
-  for (int k = 0; k < kHidden; ++k) {
-    const int h = clamp_i(hidden_pre(net.w1[k], net.b1[k], lo, hi), 0, 0x7fffff);
-    acc += h * ((net.w2[k] << 24) >> 24);
+  for (int g = 0; g < 4; ++g) {
+    const v4i d = __builtin_amdgcn_mfma_i32_16x16x32_i8(m.a[g], b, m.bias, 0, 0, 0);
+    int sum = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sum += clamp_i(d[r], 0, 0x7fffff) * m.w2[r];
+    sum += __shfl_xor(sum, 16);
+    sum += __shfl_xor(sum, 32);
+    if ((lane >> 4) == g) mine = sum;
   }
-  return clamp_i(acc >> net.shift, -255, 255);
+  return clamp_i((mine + m.b2) >> m.shift, -255, 255);
+}
+
+// Stage the network in LDS (one copy per block) for mfma_net.
+__device__ __forceinline__ void stage_net(uint32_t *s_net, const Net &net) {
+  const int t = int(threadIdx.x);
+  if (t < 32) s_net[t] = net.w1[t >> 1][t & 1];
+  else if (t < 48) s_net[t] = uint32_t(net.b1[t - 32]);
+  else if (t < 64) s_net[t] = uint32_t(net.w2[t - 48]);
 }
 
 // whole-sample symmetric index for a signal of length N
@@ -238,9 +288,11 @@ __global__ __launch_bounds__(256) void lfwd_kernel(Src src, Sink sink, const Net
   __shared__ int32_t sE[T::NE * LINES];
   __shared__ int32_t sO[T::NO * LINES];
   __shared__ int32_t sD[T::NO * LINES];
+  __shared__ uint32_t s_net[64];
   int s0, l0;
   tile_coords(n_seg, SEG, LINES, &s0, &l0);
   const int tid = int(threadIdx.x);
+  stage_net(s_net, net);
 
   // positions s0-8 .. s0+SEG+7 (mirrored), split by parity
   for (int idx = tid; idx < (SEG + 2 * kHalo) * LINES; idx += T::kThreads) {
@@ -255,17 +307,25 @@ __global__ __launch_bounds__(256) void lfwd_kernel(Src src, Sink sink, const Net
   }
   __syncthreads();
 
-  // predict, eq. (5.1) plus the correction, at odd i = s0 - 1 + 2q
-  for (int idx = tid; idx < T::NO * LINES; idx += T::kThreads) {
-    const int li = idx % LINES, q = idx / LINES, line = l0 + li;
+  // predict, eq. (5.1) plus the correction, at odd i = s0 - 1 + 2q; the
+  // loop trip count is uniform per wavefront (the network runs on the matrix
+  // cores with every lane active), lanes past the end only pad
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const MfmaNet mn = mfma_net(s_net, net.b2, net.shift, lane);
+  for (int base0 = wave * 64; base0 < T::NO * LINES; base0 += T::kThreads) {
+    const int idx = base0 + lane;
+    const bool in = idx < T::NO * LINES;
+    const int li = in ? idx % LINES : 0, q = in ? idx / LINES : 0, line = l0 + li;
     const int i = s0 - 1 + 2 * q;
-    if (i <= 0 || i >= N || line >= n_lines) continue;
+    const bool valid = in && i > 0 && i < N && line < n_lines;
     int e[kCtx];
 #pragma unroll
     for (int j = 0; j < kCtx; ++j) e[j] = sE[(q + j) * LINES + li];
     const int base = (e[3] + e[4]) >> 1;
+    const int corr = correction_mfma(mn, e, base, lane);
+    if (!valid) continue;
     const int x = sO[q * LINES + li];
-    sD[q * LINES + li] = x - base - correction(net, e, base);
+    sD[q * LINES + li] = x - base - corr;
     if (CAPTURE && q >= 1 && i < s0 + SEG) {
       int c[kCtx];
 #pragma unroll
@@ -299,9 +359,11 @@ __global__ __launch_bounds__(256) void linv_kernel(Src src, Out out, const Net n
                                                    int n_lines, int n_seg) {
   using T = Tile<LINES, SEG>;
   __shared__ int32_t sE[T::NE * LINES];
+  __shared__ uint32_t s_net[64];
   int s0, l0;
   tile_coords(n_seg, SEG, LINES, &s0, &l0);
   const int tid = int(threadIdx.x);
+  stage_net(s_net, net);
 
   // undo the update at the (mirrored) even positions s0-8 .. s0+SEG+6
   for (int idx = tid; idx < T::NE * LINES; idx += T::kThreads) {
@@ -320,20 +382,24 @@ __global__ __launch_bounds__(256) void linv_kernel(Src src, Out out, const Net n
   }
   __syncthreads();
 
-  // owned positions: evens as rebuilt, odds by undoing the predict
-  for (int idx = tid; idx < (SEG / 2) * LINES; idx += T::kThreads) {
-    const int li = idx % LINES, e2 = idx / LINES, line = l0 + li;
+  // owned positions: evens as rebuilt, odds by undoing the predict (the
+  // network on the matrix cores: uniform trip count per wavefront)
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const MfmaNet mn = mfma_net(s_net, net.b2, net.shift, lane);
+  for (int base0 = wave * 64; base0 < (SEG / 2) * LINES; base0 += T::kThreads) {
+    const int idx = base0 + lane;
+    const bool in = idx < (SEG / 2) * LINES;
+    const int li = in ? idx % LINES : 0, e2 = in ? idx / LINES : 0, line = l0 + li;
     const int i = s0 + 2 * e2;
-    if (i >= N || line >= n_lines) continue;
-    out(line, i, sE[(e2 + 4) * LINES + li]);
-    if (i + 1 < N) {
-      const int q = e2 + 1;
-      int e[kCtx];
+    const bool valid = in && i < N && line < n_lines;
+    if (valid) out(line, i, sE[(e2 + 4) * LINES + li]);
+    const int q = e2 + 1;
+    int e[kCtx];
 #pragma unroll
-      for (int j = 0; j < kCtx; ++j) e[j] = sE[(q + j) * LINES + li];
-      const int base = (e[3] + e[4]) >> 1;
-      out(line, i + 1, src.high(line, i >> 1) + base + correction(net, e, base));
-    }
+    for (int j = 0; j < kCtx; ++j) e[j] = sE[(q + j) * LINES + li];
+    const int base = (e[3] + e[4]) >> 1;
+    const int corr = correction_mfma(mn, e, base, lane);
+    if (valid && i + 1 < N) out(line, i + 1, src.high(line, i >> 1) + base + corr);
   }
 }
 
