@@ -144,6 +144,22 @@ int dwtfrag_batch_create(const dwtfrag_item *items, uint32_t count, const dwtfra
     for (int w = 0; w < bi.fwd.n_waves; ++w) ft[cf].push_back(make_int2(int(i), w));
     for (int w = 0; w < bi.inv.n_waves; ++w) it[ci].push_back(make_int2(int(i), w));
   }
+  // Longest tiles first within a queue, so the short tiles of small items
+  // fill the end of a drain instead of extending it.  A tile's cost is the
+  // rows it streams (segment plus halos) times the columns of its window.
+  const auto tile_cost = [](const StageParams &P) {
+    const int64_t seg = int64_t(P.unit_rows) * ((P.units + P.n_seg - 1) / P.n_seg);
+    return std::min<int64_t>(P.H, seg + P.halo_t + P.halo_b) * std::min(P.W, P.own_w);
+  };
+  std::vector<int64_t> fcost(count), icost(count);
+  for (uint32_t i = 0; i < count; ++i) {
+    fcost[i] = tile_cost(b->items[i].fwd);
+    icost[i] = tile_cost(b->items[i].inv);
+  }
+  for (auto &v : ft)
+    std::stable_sort(v.begin(), v.end(), [&](const int2 &x, const int2 &y) { return fcost[x.x] > fcost[y.x]; });
+  for (auto &v : it)
+    std::stable_sort(v.begin(), v.end(), [&](const int2 &x, const int2 &y) { return icost[x.x] > icost[y.x]; });
   for (size_t c = 0; c < b->fwd_cls.size(); ++c) {
     b->fwd_cls[c].tile_off = int64_t(b->tiles.size());
     b->fwd_cls[c].n_tiles = int64_t(ft[c].size());
