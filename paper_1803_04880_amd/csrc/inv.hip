@@ -10,6 +10,7 @@
 // for level l-1.  Level 1 emits output rows.
 #include "batch.h"
 #include "lift.h"
+#include "pack.h"
 
 namespace dwtfrag {
 
@@ -231,6 +232,315 @@ struct InvWave {
   }
 };
 
+// Packed form of the same stream (two int16 samples per register, the
+// forward's layout: E = lows, O = highs, see pack.h).  Exact when every value
+// a level reads (LL row, HL, LH, HH) lies in [-4096, 4095]: then the vertical
+// inverse gives |x| <= 10240, the horizontal one evens <= 15360 and odds
+// <= 25600, and no sum exceeds 30720, so 16 bits never wrap.  Fragments made
+// by protect stay far inside that range.  The stream checks every value it
+// reads; run() returns false when one was outside, and the caller then redoes
+// the wavefront's rectangle with the 32-bit stream above (same output bytes
+// as the exact integer inverse for any fragments).
+template <int L, int C1, bool U8OUT>
+struct InvWavePk {
+  template <int l> static constexpr int M = (C1 >> (l - 1)) / 2;  // evens per lane at level l
+  template <int l> static constexpr int NP = Pk<M<l>>::P;         // words per parity
+  template <int l> static constexpr int R = 2 * NP<l>;            // words per row: E then O
+  static constexpr uint32_t kBias = 0x10001000u;   // [-4096, 4095] -> [0, 8191]
+  static constexpr uint32_t kOutside = 0xE000E000u;
+
+  const StageParams &P;
+  const int16_t *llin;
+  const int16_t *pub;
+  uint8_t *out8;
+  int16_t *out16;
+  KsRing ks;
+  int lane;
+  int c0;
+  int X0, Y0, X1, Y1;
+  bool last_win, last_seg;
+  uint32_t chk;            // OR of every biased value read
+
+  // detail rows of the next step of each level, as loaded (band order is
+  // the packed order: HL / HH words are O words, LH words E words)
+  uint32_t Fh1[NP<1>], Fl1[NP<1>], Fx1[NP<1>];
+  uint32_t Fh2[NP<2>], Fl2[NP<2>], Fx2[NP<2>];
+  uint32_t Fh3[NP<3>], Fl3[NP<3>], Fx3[NP<3>];
+  uint32_t Fh4[NP<4>], Fl4[NP<4>], Fx4[NP<4>];
+  // vertical state: previous detail row and previous even row (E then O)
+  uint32_t Dp1[R<1>], Xp1[R<1>];
+  uint32_t Dp2[R<2>], Xp2[R<2>];
+  uint32_t Dp3[R<3>], Xp3[R<3>];
+  uint32_t Dp4[R<4>], Xp4[R<4>];
+  int k0[kMaxFused + 1];
+  bool hedge[kMaxFused + 1];
+
+  template <int l> __device__ auto &Dp() {
+    if constexpr (l == 1) return Dp1; else if constexpr (l == 2) return Dp2;
+    else if constexpr (l == 3) return Dp3; else return Dp4;
+  }
+  template <int l> __device__ auto &Xp() {
+    if constexpr (l == 1) return Xp1; else if constexpr (l == 2) return Xp2;
+    else if constexpr (l == 3) return Xp3; else return Xp4;
+  }
+  template <int l> __device__ auto &Fh() {
+    if constexpr (l == 1) return Fh1; else if constexpr (l == 2) return Fh2;
+    else if constexpr (l == 3) return Fh3; else return Fh4;
+  }
+  template <int l> __device__ auto &Fl() {
+    if constexpr (l == 1) return Fl1; else if constexpr (l == 2) return Fl2;
+    else if constexpr (l == 3) return Fl3; else return Fl4;
+  }
+  template <int l> __device__ auto &Fx() {
+    if constexpr (l == 1) return Fx1; else if constexpr (l == 2) return Fx2;
+    else if constexpr (l == 3) return Fx3; else return Fx4;
+  }
+
+  template <int n> __device__ __forceinline__ void check(const uint32_t (&w)[n]) {
+    if constexpr (n == 1) {
+      chk |= pk_add(w[0], kBias);
+    } else {
+#pragma unroll
+      for (int j = 0; j + 1 < n; j += 2) chk = chk | pk_add(w[j], kBias) | pk_add(w[j + 1], kBias);
+    }
+  }
+
+  template <int l> __device__ __forceinline__ void prefetch(int k) {
+    constexpr int UU = M<l>;
+    const int N = P.hdim[l - 1];
+    const int Nw = P.wdim[l - 1];
+    const int wl = P.wdim[l];
+    const int bc = c0 >> l;
+    if (k < P.hdim[l])
+      load_raw<UU>(pub + P.off_hl[l], int64_t(k) * (Nw - wl) + bc, (Nw - wl) - bc, Fh<l>());
+    if (2 * k + 1 < N) {
+      load_raw<UU>(pub + P.off_lh[l], int64_t(k) * wl + bc, wl - bc, Fl<l>());
+      load_raw<UU>(pub + P.off_hh[l], int64_t(k) * (Nw - wl) + bc, (Nw - wl) - bc, Fx<l>());
+    }
+  }
+
+  // Row i of the level-(l-1) grid after the vertical inverse of level l.
+  template <int l> __device__ __forceinline__ void emit_row(const uint32_t (&x)[R<l>], int i) {
+    constexpr int Np = NP<l>;
+    uint32_t E[Np], O[Np];
+#pragma unroll
+    for (int j = 0; j < Np; ++j) { E[j] = x[j]; O[j] = x[Np + j]; }
+    hinv_pk_any<M<l>>(E, O, c0 >> (l - 1), P.wdim[l - 1], hedge[l]);
+    if constexpr (l > 1) {
+      // the row in memory order is the LL row of level l-1
+      uint32_t ll[NP<l - 1>];
+#pragma unroll
+      for (int j = 0; j < Np; ++j) {
+        ll[2 * j] = lo_halves(E[j], O[j]);
+        if constexpr (M<l> >= 2) ll[2 * j + 1] = hi_halves(E[j], O[j]);
+      }
+      push_ll<l - 1>(ll, i);
+    } else {
+      if (i < Y0 || (!last_seg && i >= Y1)) return;
+      if (c0 < X0 || (!last_win && c0 >= X1)) return;
+      const int64_t idx = int64_t(i) * P.W + c0;
+      if constexpr (U8OUT) {
+        // bytes of this lane's columns inside the view: the row's end, and n
+        const int64_t lim = min(int64_t(P.W - c0), P.n_valid - idx);
+        uint32_t w[C1 / 4];
+#pragma unroll
+        for (int q = 0; q < C1 / 4; ++q) w[q] = __builtin_amdgcn_perm(O[q], E[q], 0x06020400u);
+        if (lim >= C1 && (idx & (C1 - 1)) == 0) {
+          if constexpr (C1 == 8) *reinterpret_cast<uint2 *>(out8 + idx) = make_uint2(w[0], w[1]);
+          else *reinterpret_cast<uint4 *>(out8 + idx) = make_uint4(w[0], w[1], w[2], w[3]);
+        } else {
+#pragma unroll
+          for (int t = 0; t < C1; ++t)
+            if (t < lim) out8[idx + t] = uint8_t(w[t >> 2] >> (8 * (t & 3)));
+        }
+      } else {
+        uint32_t w[C1 / 2];
+#pragma unroll
+        for (int q = 0; q < C1 / 4; ++q) {
+          w[2 * q] = lo_halves(E[q], O[q]);
+          w[2 * q + 1] = hi_halves(E[q], O[q]);
+        }
+        const int64_t lim = int64_t(P.W - c0);
+        if (lim >= C1 && (idx & (C1 - 1)) == 0) {
+#pragma unroll
+          for (int q = 0; q < C1 / 8; ++q)
+            reinterpret_cast<uint4 *>(out16 + idx)[q] =
+                make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+        } else {
+#pragma unroll
+          for (int t = 0; t < C1; ++t)
+            if (t < lim) out16[idx + t] = int16_t(uint16_t(w[t >> 1] >> (16 * (t & 1))));
+        }
+      }
+    }
+  }
+
+  // Step k of level l: LL_l row k arrives as E words (band order).
+  template <int l> __device__ __forceinline__ void push_ll(const uint32_t (&ll)[NP<l>], int k) {
+    constexpr int Np = NP<l>;
+    constexpr int Rl = R<l>;
+    const int N = P.hdim[l - 1];
+    uint32_t S[Rl];
+#pragma unroll
+    for (int j = 0; j < Np; ++j) { S[j] = ll[j]; S[Np + j] = Fh<l>()[j]; }
+    check(S);
+    auto &Dv = Dp<l>();
+    auto &Xv = Xp<l>();
+    uint32_t Ra[Rl], Rb[Rl];   // rows 2k-1 and 2k
+    bool last_pair = false;
+    int e_begin = 1;
+    if (N == 1) {  // no vertical pass at this level: the row is row 0
+#pragma unroll
+      for (int t = 0; t < Rl; ++t) Rb[t] = S[t];
+    } else {
+      uint32_t Dn[Rl];
+      if (2 * k + 1 < N) {
+#pragma unroll
+        for (int j = 0; j < Np; ++j) { Dn[j] = Fl<l>()[j]; Dn[Np + j] = Fx<l>()[j]; }
+        check(Dn);
+      } else {  // odd length, last step: d(N) = d(N-2)
+#pragma unroll
+        for (int t = 0; t < Rl; ++t) Dn[t] = Dv[t];
+      }
+      prefetch<l>(k + 1);
+      const bool top = (k == 0);
+#pragma unroll
+      for (int t = 0; t < Rl; ++t) {
+        const uint32_t X = pk_sub(S[t], pk_sra(pk_add(pk_add(top ? Dn[t] : Dv[t], Dn[t]), 0x00020002u), 2));
+        Ra[t] = pk_add(Dv[t], pk_sra(pk_add(Xv[t], X), 1));
+        Rb[t] = X;
+        Dv[t] = Dn[t];
+        Xv[t] = X;
+      }
+      last_pair = (2 * k + 1 == N - 1);  // even length: row 2k+1 = d + x(2k)
+      if (k != k0[l]) e_begin = 0;
+    }
+    const int e_end = last_pair ? 3 : 2;
+    // one call site per level: the rows go through a loop
+#pragma unroll 1
+    for (int e = e_begin; e < e_end; ++e) {
+      uint32_t row[Rl];
+#pragma unroll
+      for (int t = 0; t < Rl; ++t) row[t] = (e & 1) ? Rb[t] : Ra[t];
+      emit_row<l>(row, 2 * k - 1 + e);
+      if (e == 1 && last_pair) {
+#pragma unroll
+        for (int t = 0; t < Rl; ++t) Ra[t] = pk_add(Dv[t], Xv[t]);
+      }
+    }
+  }
+
+  __device__ __forceinline__ void load_ll(int k, uint32_t (&ll)[NP<L>]) {
+    const int wl = P.wdim[L];
+    const int bc = c0 >> L;
+    load_raw<M<L>>(llin, int64_t(k) * wl + bc, wl - bc, ll);
+  }
+
+  // Returns false when a value outside [-4096, 4095] was read (the packed
+  // results are then not trusted).
+  __device__ __forceinline__ bool run(int wave) {
+    const int win = wave % P.n_win;
+    const int seg = wave / P.n_win;
+    X0 = win * P.own_w;
+    last_win = (win == P.n_win - 1);
+    last_seg = (seg == P.n_seg - 1);
+    Y0 = seg_start(P, seg);
+    X1 = last_win ? P.W : X0 + P.own_w;
+    Y1 = last_seg ? P.H : seg_start(P, seg + 1);
+    const int cbase = (win == 0) ? 0 : X0 - P.halo_l;
+    c0 = cbase + lane * C1;
+    const int kbeg = (Y0 > P.halo_t ? Y0 - P.halo_t : 0) >> L;
+    const int kend = min(P.hdim[L], (Y1 + P.halo_b) >> L);
+#pragma unroll
+    for (int l = 1; l <= L; ++l) {
+      k0[l] = kbeg << (L - l);
+      const int N = P.wdim[l - 1];
+      const int j0 = cbase >> (l - 1);
+      const int span = (64 * C1) >> (l - 1);
+      hedge[l] = (j0 == 0) || (N - 1 >= j0 && N - 1 < j0 + span);
+    }
+    chk = 0;
+#pragma unroll
+    for (int t = 0; t < R<1>; ++t) { Dp1[t] = 0; Xp1[t] = 0; }
+#pragma unroll
+    for (int t = 0; t < R<2>; ++t) { Dp2[t] = 0; Xp2[t] = 0; }
+#pragma unroll
+    for (int t = 0; t < R<3>; ++t) { Dp3[t] = 0; Xp3[t] = 0; }
+#pragma unroll
+    for (int t = 0; t < R<4>; ++t) { Dp4[t] = 0; Xp4[t] = 0; }
+    ks.col_lo = min(P.wdim[L], cbase >> L);
+    ks.col_hi = min(P.wdim[L], (cbase + 64 * C1) >> L);
+    ks.wL = P.wdim[L];
+    ks.base = -1;
+
+    if (kbeg >= kend) return true;
+    prefetch<1>(k0[1]);
+    if constexpr (L >= 2) prefetch<2>(k0[2]);
+    if constexpr (L >= 3) prefetch<3>(k0[3]);
+    if constexpr (L >= 4) prefetch<4>(k0[4]);
+    constexpr int Np = NP<L>;
+    uint32_t nxt[Np];
+    load_ll(kbeg, nxt);
+    for (int k = kbeg; k < kend; ++k) {
+      uint32_t cur[Np];
+#pragma unroll
+      for (int j = 0; j < Np; ++j) cur[j] = nxt[j];
+      if (k + 1 < kend) load_ll(k + 1, nxt);
+      if (P.use_aes) {
+        ks.ensure(k, kend, lane);
+        const int bc = c0 >> L;
+        const int nv = P.wdim[L] - bc;
+#pragma unroll
+        for (int u = 0; u < (M<L> >= 2 ? 2 * Np : 1); ++u)
+          if (u < nv) cur[u >> 1] ^= ks.ks16(k, bc + u) << (16 * (u & 1));
+      }
+      push_ll<L>(cur, k);
+    }
+    return __builtin_amdgcn_ballot_w64((chk & kOutside) != 0) == 0;
+  }
+};
+
+template <class Wv>
+__device__ __forceinline__ void inv_setup(Wv &w, const int16_t *llin, const int16_t *pub, void *out,
+                                          int lane, uint32_t *ring, const uint32_t *te,
+                                          const uint32_t *kw) {
+  w.llin = llin;
+  w.pub = pub;
+  w.out8 = static_cast<uint8_t *>(out);
+  w.out16 = static_cast<int16_t *>(out);
+  w.lane = lane;
+  w.ks.ring = ring;
+  w.ks.te = te;
+  w.ks.kw = kw;
+  w.ks.rows = w.P.ks_rows;
+  w.ks.blocks = w.P.ks_blocks;
+}
+
+// The 32-bit stream as a function of its own: kept out of line so that its
+// registers do not add to the packed stream's; it reads the plan through a
+// pointer (a copy in LDS, or the batch item in device memory).
+template <int L, int C1, bool U8OUT>
+__device__ __noinline__ void inv_wave_exact(const StageParams *P, int wave, const int16_t *llin,
+                                            const int16_t *pub, void *out, int lane, uint32_t *ring,
+                                            const uint32_t *te, const uint32_t *kw) {
+  InvWave<L, C1, U8OUT> x{*P};
+  inv_setup(x, llin, pub, out, lane, ring, te, kw);
+  x.run(wave);
+}
+
+// One wavefront's rectangle: the packed stream, redone with the 32-bit
+// stream when a value fell outside the packed range.
+template <int L, int C1, bool U8OUT>
+__device__ __forceinline__ void inv_wave(const StageParams &P, const StageParams *Pmem, int wave,
+                                         const int16_t *llin, const int16_t *pub, void *out, int lane,
+                                         uint32_t *ring, const uint32_t *te, const uint32_t *kw) {
+  InvWavePk<L, C1, U8OUT> w{P};
+  inv_setup(w, llin, pub, out, lane, ring, te, kw);
+  if (w.run(wave)) return;
+  wave_lds_sync();
+  inv_wave_exact<L, C1, U8OUT>(Pmem, wave, llin, pub, out, lane, ring, te, kw);
+}
+
 template <int L, int C1, bool U8OUT>
 __device__ __forceinline__ void inv_body(const int16_t *__restrict__ llin,
                                          const int16_t *__restrict__ pub, void *__restrict__ out,
@@ -238,25 +548,19 @@ __device__ __forceinline__ void inv_body(const int16_t *__restrict__ llin,
   __shared__ uint32_t s_te[1024];
   __shared__ uint32_t s_kw[kKeyWords];
   __shared__ uint32_t s_ring[kWavesPerBlock][kRingBlocks * 4];
+  __shared__ StageParams s_P;   // the plan as the exact stream reads it
+  static_assert(sizeof(StageParams) % 4 == 0, "plan copied as words");
   if (P.use_aes) load_aes_tables(s_te, s_kw, P.key);
+  for (int i = threadIdx.x; i < int(sizeof(StageParams) / 4); i += blockDim.x)
+    reinterpret_cast<uint32_t *>(&s_P)[i] = reinterpret_cast<const uint32_t *>(&P)[i];
   __syncthreads();
   // the wavefront index is uniform; readfirstlane lets the compiler see that,
   // so all row / level bookkeeping derived from it stays scalar
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wave = blockIdx.x * kWavesPerBlock + wib;
   if (wave >= P.n_waves) return;
-  InvWave<L, C1, U8OUT> w{P};
-  w.llin = llin;
-  w.pub = pub;
-  w.out8 = static_cast<uint8_t *>(out);
-  w.out16 = static_cast<int16_t *>(out);
-  w.lane = threadIdx.x & 63;
-  w.ks.ring = s_ring[wib];
-  w.ks.te = s_te;
-  w.ks.kw = s_kw;
-  w.ks.rows = P.ks_rows;
-  w.ks.blocks = P.ks_blocks;
-  w.run(wave);
+  inv_wave<L, C1, U8OUT>(P, &s_P, wave, llin, pub, out, int(threadIdx.x & 63), s_ring[wib], s_te,
+                         s_kw);
 }
 
 // Eight columns per lane: held to 128 VGPRs (four wavefronts per SIMD), the
@@ -268,12 +572,12 @@ void inv_kernel8(const int16_t *__restrict__ llin, const int16_t *__restrict__ p
   inv_body<L, 8, U8OUT>(llin, pub, out, P);
 }
 
-// Sixteen columns per lane need more registers than that.
+// Sixteen columns per lane need more registers than that: two wavefronts
+// per SIMD (256 VGPRs, which also bounds the out-of-line exact stream).
 template <int L, bool U8OUT>
-__global__ __launch_bounds__(kBlockThreads) void inv_kernel16(const int16_t *__restrict__ llin,
-                                                             const int16_t *__restrict__ pub,
-                                                             void *__restrict__ out,
-                                                             const StageParams P) {
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void inv_kernel16(const int16_t *__restrict__ llin, const int16_t *__restrict__ pub,
+                  void *__restrict__ out, const StageParams P) {
   inv_body<L, 16, U8OUT>(llin, pub, out, P);
 }
 
@@ -332,18 +636,8 @@ __device__ __forceinline__ void inv_batch_body(const BatchItem *__restrict__ ite
       s_kw[wib][lane] = v;
     }
     wave_lds_sync();
-    InvWave<L, C1, true> w{it.inv};
-    w.llin = reinterpret_cast<const int16_t *>(it.priv);
-    w.pub = it.pub;
-    w.out8 = it.out;
-    w.out16 = nullptr;
-    w.lane = lane;
-    w.ks.ring = s_ring[wib];
-    w.ks.te = s_te;
-    w.ks.kw = s_kw[wib];
-    w.ks.rows = it.inv.ks_rows;
-    w.ks.blocks = it.inv.ks_blocks;
-    w.run(e.y);
+    inv_wave<L, C1, true>(it.inv, &it.inv, e.y, reinterpret_cast<const int16_t *>(it.priv), it.pub, it.out, lane,
+                          s_ring[wib], s_te, s_kw[wib]);
     wave_lds_sync();
   }
 }
@@ -356,10 +650,9 @@ void inv_batch_kernel8(const BatchItem *__restrict__ items, const int2 *__restri
 }
 
 template <int L>
-__global__ __launch_bounds__(kBlockThreads) void inv_batch_kernel16(const BatchItem *__restrict__ items,
-                                                                   const int2 *__restrict__ tiles,
-                                                                   int64_t n_tiles,
-                                                                   unsigned int *__restrict__ head) {
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void inv_batch_kernel16(const BatchItem *__restrict__ items, const int2 *__restrict__ tiles,
+                        int64_t n_tiles, unsigned int *__restrict__ head) {
   inv_batch_body<L, 16>(items, tiles, n_tiles, head);
 }
 

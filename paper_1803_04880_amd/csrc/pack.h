@@ -1,8 +1,10 @@
-// Packed 16-bit lifting arithmetic for the forward path.
+// Packed 16-bit lifting arithmetic.
 //
 // Forward coefficients of byte inputs stay far inside int16 (|c| < 1100 at any
 // depth; sums of two stay below 2^12), so two samples share one 32-bit
 // register and every lifting operation is one v_pk_* instruction on both.
+// The inverse runs on the same layout when its inputs are bounded (see
+// hinv_pk and the inverse kernel's range check).
 //
 // Register layout at a level where a lane holds M even and M odd samples
 // (indices j0 .. j0+2M-1, j0 even) in P = max(1, M/2) registers per parity:
@@ -98,6 +100,42 @@ __device__ __forceinline__ void hfwd_pk_any(uint32_t (&E)[Pk<M>::P], uint32_t (&
   if (N == 1) return;
   if (edge) hfwd_pk<M, true>(E, O, j0, N);
   else hfwd_pk<M, false>(E, O, j0, N);
+}
+
+// Inverse of hfwd_pk: E holds lows, O highs; undo the update (5.2) on the
+// evens, then the predict (5.1) on the odds.  The same neighbour pairs and
+// mirror rules as the forward, taken in reverse order.
+template <int M, bool EDGE>
+__device__ __forceinline__ void hinv_pk(uint32_t (&E)[Pk<M>::P], uint32_t (&O)[Pk<M>::P], int j0, int N) {
+  constexpr int P = Pk<M>::P;
+  int tgt = N - 1 - j0;
+  if (EDGE) asm volatile("" : "+v"(tgt), "+v"(j0));
+  const uint32_t prv = uint32_t(from_prev_lane(int(O[P - 1])));
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    uint32_t dl = (j > 0) ? align16(O[j], O[j - 1]) : (M >= 2 ? align16(O[0], prv) : prv);
+    uint32_t dr = O[j];
+    if (EDGE) {
+      if (j == 0) dl = bsel(j0 == 0 ? 0x0000FFFFu : 0u, O[0], dl);  // d(-1) = d(1)
+      dr = bsel(half_at(tgt, 4 * j), dl, dr);                       // d(N) = d(N-2)
+    }
+    E[j] = pk_sub(E[j], pk_sra(pk_add(pk_add(dl, dr), 0x00020002u), 2));
+  }
+  const uint32_t nxt = uint32_t(from_next_lane(int(E[0])));
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    uint32_t en = (j + 1 < P) ? align16(E[j + 1], E[j]) : (M >= 2 ? align16(nxt, E[j]) : nxt);
+    if (EDGE) en = bsel(half_at(tgt, 4 * j + 1), E[j], en);   // x(N) = x(N-2)
+    O[j] = pk_add(O[j], pk_sra(pk_add(E[j], en), 1));
+  }
+}
+
+template <int M>
+__device__ __forceinline__ void hinv_pk_any(uint32_t (&E)[Pk<M>::P], uint32_t (&O)[Pk<M>::P], int j0,
+                                            int N, bool edge) {
+  if (N == 1) return;
+  if (edge) hinv_pk<M, true>(E, O, j0, N);
+  else hinv_pk<M, false>(E, O, j0, N);
 }
 
 }  // namespace dwtfrag

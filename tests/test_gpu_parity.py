@@ -85,6 +85,72 @@ def test_restore_of_arbitrary_fragments_matches_oracle(n, width, levels):
     assert got == fragment.restore(priv, pub, n, width, levels, key, nonce)
 
 
+def _fragments_from_values(ll, pub, key, nonce):
+    """Fragments holding the given LL plaintext and public coefficients."""
+    priv = aes128.ctr_xor(key, nonce, np.asarray(ll, "<i2").tobytes()).tobytes()
+    return priv, np.asarray(pub, "<i2").tobytes()
+
+
+@pytest.mark.parametrize("n,width", [(100003, 317), (262144, 512), (513 * 37, 513)])
+def test_restore_at_the_packed_range_limits(n, width):
+    """One level, every coefficient in [-4096, 4095] and half of them at the
+    two ends: the 16-bit inverse runs at its largest sums and must still give
+    the exact integer inverse."""
+    rng = np.random.default_rng(n + 1)
+    g = fragment.geometry(n, width, 1)
+    key, nonce = rng.bytes(16), rng.bytes(16)
+
+    def draw(count):
+        v = rng.integers(-4096, 4096, count)
+        ends = rng.random(count) < 0.5
+        v[ends] = np.where(rng.random(int(ends.sum())) < 0.5, -4096, 4095)
+        return v
+
+    priv, pub = _fragments_from_values(draw(g["priv_bytes"] // 2), draw(g["pub_bytes"] // 2), key, nonce)
+    _say(f"range limits n={n} width={width}")
+    got = _gpu_restore(priv, pub, n, width, 1, key, nonce)
+    assert got == fragment.restore(priv, pub, n, width, 1, key, nonce)
+
+
+@pytest.mark.parametrize("levels,where,value", [
+    (1, "pub", 4096), (1, "ll", -4097), (2, "pub", -4097), (2, "ll", 4096), (3, "pub", 30000),
+    (3, "ll", -32768), (4, "pub", 4096),
+])
+def test_restore_with_one_value_outside_packed_range(levels, where, value):
+    """Fragments of real data with one coefficient moved just outside the
+    16-bit stream's range: the wavefronts that read it redo their rectangle
+    in 32 bits, the others keep the packed result; all bytes must equal the
+    exact inverse."""
+    n, width = 300000, 1031
+    rng = np.random.default_rng(levels * 10 + len(where))
+    buf = rng.integers(0, 256, n, dtype=np.uint8)
+    key, nonce = rng.bytes(16), rng.bytes(16)
+    opriv, opub = fragment.protect(buf, width, levels, key, nonce)
+    ll = np.frombuffer(aes128.ctr_xor(key, nonce, opriv).tobytes(), "<i2").copy()
+    pub = np.frombuffer(opub, "<i2").copy()
+    target = ll if where == "ll" else pub
+    target[int(rng.integers(0, target.size))] = value
+    priv, pubb = _fragments_from_values(ll, pub, key, nonce)
+    _say(f"one value outside: levels={levels} {where}={value}")
+    got = _gpu_restore(priv, pubb, n, width, levels, key, nonce)
+    assert got == fragment.restore(priv, pubb, n, width, levels, key, nonce)
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_restore_of_small_arbitrary_fragments(levels):
+    """Arbitrary coefficients in [-600, 600] (LL included): packed where the
+    reconstructed rows stay in range, 32-bit where they do not."""
+    n, width = 200003, 613
+    rng = np.random.default_rng(70 + levels)
+    g = fragment.geometry(n, width, levels)
+    key, nonce = rng.bytes(16), rng.bytes(16)
+    priv, pub = _fragments_from_values(rng.integers(-600, 601, g["priv_bytes"] // 2),
+                                       rng.integers(-600, 601, g["pub_bytes"] // 2), key, nonce)
+    _say(f"small arbitrary fragments levels={levels}")
+    got = _gpu_restore(priv, pub, n, width, levels, key, nonce)
+    assert got == fragment.restore(priv, pub, n, width, levels, key, nonce)
+
+
 LAUNCHES = [None, (8, 8), (16, 8), (24, 16), (64, 16), (200, 8)]
 
 
