@@ -61,6 +61,17 @@ struct FwdWave {
   int qn[kMaxFused + 1];    // rows waiting in each level's queue this batch
   bool hedge[kMaxFused + 1];
   bool lown[kMaxFused + 1];
+  // Direct band stores (a wave-uniform choice per level): every lane keeps a
+  // pointer to its columns of the next owned row of HL and LH (and of the LL
+  // output) and advances it by the band's row length after each row; the HH
+  // row sits at a fixed distance from the HL row.  Used when no lane of the
+  // wavefront holds a partial vector and every row of the level's bands is
+  // vector aligned; otherwise store_band.
+  bool fast[kMaxFused + 1];
+  char *pHL[kMaxFused + 1], *pLH[kMaxFused + 1], *pLL;
+  int64_t dHH[kMaxFused + 1];                       // HH row - HL row (bytes)
+  uint32_t sLo[kMaxFused + 1], sHi[kMaxFused + 1];  // bytes per row step
+  bool flo[kMaxFused + 1], fhi[kMaxFused + 1];      // lane stores this class
 
   template <int l> __device__ __forceinline__ auto &E() {
     if constexpr (l == 1) return E1; else if constexpr (l == 2) return E2;
@@ -106,6 +117,14 @@ struct FwdWave {
       if (u < nvalid) dst[u] = int16_t(Mv == 1 ? V[0] : (V[u >> 1] >> (16 * (u & 1))));
   }
 
+  // Mv int16 values at an aligned address (Mv-element vector).
+  template <int Mv> __device__ __forceinline__ static void store_vec(char *p, const uint32_t *V) {
+    if constexpr (Mv == 1) *reinterpret_cast<int16_t *>(p) = int16_t(V[0]);
+    else if constexpr (Mv == 2) *reinterpret_cast<uint32_t *>(p) = V[0];
+    else if constexpr (Mv == 4) *reinterpret_cast<uint2 *>(p) = make_uint2(V[0], V[1]);
+    else *reinterpret_cast<uint4 *>(p) = make_uint4(V[0], V[1], V[2], V[3]);
+  }
+
   // Low row k of level l: lows -> LL_l (next level's queue / LL output),
   // highs -> HL_l.
   template <int l> __device__ __forceinline__ void emit_low(const uint32_t (&s)[R<l>], int k) {
@@ -114,8 +133,12 @@ struct FwdWave {
     const int wl = G.wdim[l];
     const int bc = c0 >> l;
     const bool rown = row_owned<l>(k);
-    if (rown && lown[l])
+    if (rown && fast[l]) {
+      if (fhi[l]) store_vec<M<l>>(pHL[l], s + Np);
+      pHL[l] += sHi[l];
+    } else if (rown && lown[l]) {
       store_band<M<l>>(pub + G.off_hl[l] + int64_t(k) * (N - wl), bc, (N - wl) - bc, s + Np);
+    }
     if constexpr (l < L) {
       constexpr int Mn = M<l + 1>;
       constexpr int Nn = NP<l + 1>;
@@ -135,14 +158,26 @@ struct FwdWave {
       for (int j = 0; j < Nn; ++j) { dst[j] = e[j]; dst[Nn + j] = o[j]; }
       qn[l + 1] += 1;
     } else {
-      if (rown && lown[l]) store_band<M<l>>(llout + int64_t(k) * wl, bc, wl - bc, s);
+      if (rown && fast[l]) {
+        if (flo[l]) store_vec<M<l>>(pLL, s);
+        pLL += sLo[l];
+      } else if (rown && lown[l]) {
+        store_band<M<l>>(llout + int64_t(k) * wl, bc, wl - bc, s);
+      }
     }
   }
 
   // High row k of level l: lows -> LH_l, highs -> HH_l.
   template <int l> __device__ __forceinline__ void emit_high(const uint32_t (&d)[R<l>], int k) {
-    if (!(row_owned<l>(k) && lown[l])) return;
+    if (!row_owned<l>(k)) return;
     constexpr int Np = NP<l>;
+    if (fast[l]) {
+      if (flo[l]) store_vec<M<l>>(pLH[l], d);
+      if (fhi[l]) store_vec<M<l>>(pHL[l] + dHH[l], d + Np);
+      pLH[l] += sLo[l];
+      return;
+    }
+    if (!lown[l]) return;
     const int N = G.wdim[l - 1];
     const int wl = G.wdim[l];
     const int bc = c0 >> l;
@@ -318,6 +353,28 @@ struct FwdWave {
     }
   }
 
+  template <int l> __device__ __forceinline__ void setup_stores() {
+    constexpr int Mv = M<l>;
+    const int wl = G.wdim[l];
+    const int wh = G.wdim[l - 1] - wl;
+    const int bc = c0 >> l;
+    const bool full_lo = lown[l] && wl - bc >= Mv;
+    const bool full_hi = lown[l] && wh - bc >= Mv;
+    const bool part = lown[l] && ((wl - bc > 0 && wl - bc < Mv) || (wh - bc > 0 && wh - bc < Mv));
+    const bool aligned = wl % Mv == 0 && wh % Mv == 0 && G.off_hl[l] % Mv == 0 &&
+                         G.off_lh[l] % Mv == 0 && G.off_hh[l] % Mv == 0;
+    fast[l] = aligned && __builtin_amdgcn_ballot_w64(part) == 0;
+    const int64_t k0 = Y0 >> l;  // first owned row of the level
+    pHL[l] = reinterpret_cast<char *>(pub + G.off_hl[l] + k0 * wh + bc);
+    dHH[l] = 2 * (G.off_hh[l] - G.off_hl[l]);
+    pLH[l] = reinterpret_cast<char *>(pub + G.off_lh[l] + k0 * wl + bc);
+    if constexpr (l == L) pLL = reinterpret_cast<char *>(llout + k0 * wl + bc);
+    sHi[l] = 2u * uint32_t(wh);
+    sLo[l] = 2u * uint32_t(wl);
+    flo[l] = full_lo;
+    fhi[l] = full_hi;
+  }
+
   __device__ __forceinline__ void run(int wave) {
     const int win = wave % G.n_win;
     const int seg = wave / G.n_win;
@@ -342,6 +399,10 @@ struct FwdWave {
       icnt[l] = r0 >> (l - 1);
       qn[l] = 0;
     }
+    setup_stores<1>();
+    if constexpr (L >= 2) setup_stores<2>();
+    if constexpr (L >= 3) setup_stores<3>();
+    if constexpr (L >= 4) setup_stores<4>();
 #pragma unroll
     for (int t = 0; t < R<1>; ++t) { E1[t] = 0; D1[t] = 0; P1[t] = 0; }
 #pragma unroll
