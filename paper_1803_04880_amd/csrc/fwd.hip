@@ -231,6 +231,111 @@ struct FwdWave {
     }
   }
 
+  // ---- steady-state batches ---------------------------------------------
+  // Inside the image and away from the stream's first rows, a batch hands
+  // level l a whole number of (odd, even) row pairs: level 1 gets K rows
+  // starting with an even row (completing the pair whose odd row waits in
+  // P), level l >= 2 gets K >> (l-1) rows starting with an odd row.  Such
+  // batches run without the per-row parity / first / last tests, and with
+  // the row's edge handling fixed for the whole batch.
+
+  // Pair (2k+1, 2k+2) away from the top: odd row o, even row e.
+  template <int l> __device__ __forceinline__ void pair_step(const uint32_t (&o)[R<l>],
+                                                             const uint32_t (&e)[R<l>], int k) {
+    constexpr int Rl = R<l>;
+    auto &Ev = E<l>();
+    auto &Dv = D<l>();
+    uint32_t low[Rl], high[Rl];
+#pragma unroll
+    for (int t = 0; t < Rl; ++t) {
+      const uint32_t dn = pk_predict(o[t], Ev[t], e[t]);
+      low[t] = pk_update(Ev[t], Dv[t], dn);
+      high[t] = dn;
+      Dv[t] = dn;
+      Ev[t] = e[t];
+    }
+    emit_high<l>(high, k);
+    emit_low<l>(low, k);
+  }
+
+  // Level 1: K staged rows from even row rb; requires a batch after the
+  // stream's first, rb >= 4 and rb + K < H (no first, top or last row).
+  template <bool EDGE> __device__ __forceinline__ void phase1_steady(int rb) {
+    constexpr int Np = NP<1>;
+#pragma unroll 1
+    for (int r = 0; r < K; r += 2) {
+      uint32_t x[R<1>];
+      {
+        uint32_t w[RW], Ein[Np], Oin[Np];
+        stage_read(r, w);
+        unpack(w, Ein, Oin);
+        hfwd_pk<M<1>, EDGE>(Ein, Oin, c0, G.wdim[0]);
+#pragma unroll
+        for (int j = 0; j < Np; ++j) { x[j] = Ein[j]; x[Np + j] = Oin[j]; }
+      }
+      pair_step<1>(P1, x, (rb + r - 2) >> 1);
+      {
+        uint32_t w[RW], Ein[Np], Oin[Np];
+        stage_read(r + 1, w);
+        unpack(w, Ein, Oin);
+        hfwd_pk<M<1>, EDGE>(Ein, Oin, c0, G.wdim[0]);
+#pragma unroll
+        for (int j = 0; j < Np; ++j) { P1[j] = Ein[j]; P1[Np + j] = Oin[j]; }
+      }
+    }
+    icnt[1] += K;
+  }
+
+  // Level l >= 2: n queued rows from odd row i0 = icnt[l]; requires i0 >= 3
+  // and i0 + n < N.
+  template <int l, bool EDGE> __device__ __forceinline__ void phase_steady() {
+    constexpr int Np = NP<l>;
+    const int n = qn[l];
+    const int i0 = icnt[l];
+    qn[l] = 0;
+    const uint32_t *q = queue<l>();
+    auto &Pv = Pw<l>();
+#pragma unroll 1
+    for (int r = 0; r < n; r += 2) {
+      {
+        const uint32_t *src = q + (r * 64 + lane) * R<l>;
+        uint32_t Ein[Np], Oin[Np];
+#pragma unroll
+        for (int j = 0; j < Np; ++j) { Ein[j] = src[j]; Oin[j] = src[Np + j]; }
+        hfwd_pk<M<l>, EDGE>(Ein, Oin, c0 >> (l - 1), G.wdim[l - 1]);
+#pragma unroll
+        for (int j = 0; j < Np; ++j) { Pv[j] = Ein[j]; Pv[Np + j] = Oin[j]; }
+      }
+      uint32_t x[R<l>];
+      {
+        const uint32_t *src = q + ((r + 1) * 64 + lane) * R<l>;
+        uint32_t Ein[Np], Oin[Np];
+#pragma unroll
+        for (int j = 0; j < Np; ++j) { Ein[j] = src[j]; Oin[j] = src[Np + j]; }
+        hfwd_pk<M<l>, EDGE>(Ein, Oin, c0 >> (l - 1), G.wdim[l - 1]);
+#pragma unroll
+        for (int j = 0; j < Np; ++j) { x[j] = Ein[j]; x[Np + j] = Oin[j]; }
+      }
+      pair_step<l>(Pv, x, (i0 + r - 1) >> 1);
+    }
+    icnt[l] += n;
+  }
+
+  // Level l's part of a batch: the steady form when it applies.
+  template <int l> __device__ __forceinline__ void level_phase() {
+    const int n = qn[l];
+    const int i0 = icnt[l];
+    const int N = G.hdim[l - 1];
+    const bool steady = n == (K >> (l - 1)) && n >= 2 && (i0 & 1) && i0 >= 3 && i0 + n < N &&
+                        G.wdim[l - 1] > 1;
+    if (steady) {
+      if (hedge[l]) phase_steady<l, true>();
+      else phase_steady<l, false>();
+    } else {
+      phase<l>();
+    }
+  }
+
   // ---- level phases ------------------------------------------------------
   // Level 1 consumes nb staged rows starting at level-0 row rb.
   __device__ __forceinline__ void phase1(int rb, int nb, bool staged) {
@@ -433,11 +538,16 @@ struct FwdWave {
         for (int k = 0; k < K; ++k)
           if (rn + k < r1) load_row_fast(rn + k, q[k]);  // next batch in flight
       }
-      phase1(rb, nb, fast_cur);
+      if (fast_cur && nb == K && rb != r0 && rb >= 4 && rb + K < G.H && G.W > 1) {
+        if (hedge[1]) phase1_steady<true>(rb);
+        else phase1_steady<false>(rb);
+      } else {
+        phase1(rb, nb, fast_cur);
+      }
       wave_lds_sync();
-      if constexpr (L >= 2) { phase<2>(); wave_lds_sync(); }
-      if constexpr (L >= 3) { phase<3>(); wave_lds_sync(); }
-      if constexpr (L >= 4) { phase<4>(); wave_lds_sync(); }
+      if constexpr (L >= 2) { level_phase<2>(); wave_lds_sync(); }
+      if constexpr (L >= 3) { level_phase<3>(); wave_lds_sync(); }
+      if constexpr (L >= 4) { level_phase<4>(); wave_lds_sync(); }
       if (fast_next) {
 #pragma unroll
         for (int k = 0; k < K; ++k)
