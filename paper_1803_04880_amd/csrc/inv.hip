@@ -241,7 +241,7 @@ struct InvWave {
 // reads; run() returns false when one was outside, and the caller then redoes
 // the wavefront's rectangle with the 32-bit stream above (same output bytes
 // as the exact integer inverse for any fragments).
-template <int L, int C1, bool U8OUT>
+template <int L, int C1, bool U8OUT, bool FAST>
 struct InvWavePk {
   template <int l> static constexpr int M = (C1 >> (l - 1)) / 2;  // evens per lane at level l
   template <int l> static constexpr int NP = Pk<M<l>>::P;         // words per parity
@@ -274,6 +274,13 @@ struct InvWavePk {
   uint32_t Dp4[R<4>], Xp4[R<4>];
   int k0[kMaxFused + 1];
   bool hedge[kMaxFused + 1];
+  // FAST (chosen per wavefront, see wave_is_fast): every lane's vector of
+  // every band row lies inside its band, band rows are vector aligned and
+  // every lane's output bytes lie inside a row.  Rows are then read at
+  // (uniform row address + this lane's byte offset) with no per-lane bounds,
+  // and output rows are written the same way under the column ownership.
+  uint32_t voff[kMaxFused + 1];  // this lane's byte offset in a band row of level l
+  bool own_col;                  // this lane's output columns belong to the wavefront
 
   template <int l> __device__ auto &Dp() {
     if constexpr (l == 1) return Dp1; else if constexpr (l == 2) return Dp2;
@@ -305,17 +312,44 @@ struct InvWavePk {
     }
   }
 
+  // UU int16 values at (row + off), UU-aligned: one vector load.
+  template <int UU> __device__ __forceinline__ static void load_vec(const char *row, uint32_t off,
+                                                                     uint32_t (&w)[Raw<UU>::W]) {
+    const char *p = row + off;
+    if constexpr (UU == 1) {
+      w[0] = *reinterpret_cast<const uint16_t *>(p);
+    } else if constexpr (UU == 2) {
+      w[0] = *reinterpret_cast<const uint32_t *>(p);
+    } else if constexpr (UU == 4) {
+      const uint2 q = *reinterpret_cast<const uint2 *>(p);
+      w[0] = q.x; w[1] = q.y;
+    } else {
+      const uint4 q = *reinterpret_cast<const uint4 *>(p);
+      w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
+    }
+  }
+
   template <int l> __device__ __forceinline__ void prefetch(int k) {
     constexpr int UU = M<l>;
     const int N = P.hdim[l - 1];
     const int Nw = P.wdim[l - 1];
     const int wl = P.wdim[l];
     const int bc = c0 >> l;
+    if constexpr (FAST) {
+      const char *base = reinterpret_cast<const char *>(pub);
+      if (k < P.hdim[l])
+        load_vec<UU>(base + 2 * (P.off_hl[l] + int64_t(k) * (Nw - wl)), voff[l], Fh<l>());
+      if (2 * k + 1 < N) {
+        load_vec<UU>(base + 2 * (P.off_lh[l] + int64_t(k) * wl), voff[l], Fl<l>());
+        load_vec<UU>(base + 2 * (P.off_hh[l] + int64_t(k) * (Nw - wl)), voff[l], Fx<l>());
+      }
+    } else {
     if (k < P.hdim[l])
       load_raw<UU>(pub + P.off_hl[l], int64_t(k) * (Nw - wl) + bc, (Nw - wl) - bc, Fh<l>());
     if (2 * k + 1 < N) {
       load_raw<UU>(pub + P.off_lh[l], int64_t(k) * wl + bc, wl - bc, Fl<l>());
       load_raw<UU>(pub + P.off_hh[l], int64_t(k) * (Nw - wl) + bc, (Nw - wl) - bc, Fx<l>());
+    }
     }
   }
 
@@ -337,6 +371,19 @@ struct InvWavePk {
       push_ll<l - 1>(ll, i);
     } else {
       if (i < Y0 || (!last_seg && i >= Y1)) return;
+      if constexpr (U8OUT) {
+        if (FAST && int64_t(i + 1) * P.W <= P.n_valid) {
+          uint32_t w[C1 / 4];
+#pragma unroll
+          for (int q = 0; q < C1 / 4; ++q) w[q] = __builtin_amdgcn_perm(O[q], E[q], 0x06020400u);
+          char *row = reinterpret_cast<char *>(out8) + int64_t(i) * P.W;
+          if (own_col) {
+            if constexpr (C1 == 8) *reinterpret_cast<uint2 *>(row + uint32_t(c0)) = make_uint2(w[0], w[1]);
+            else *reinterpret_cast<uint4 *>(row + uint32_t(c0)) = make_uint4(w[0], w[1], w[2], w[3]);
+          }
+          return;
+        }
+      }
       if (c0 < X0 || (!last_win && c0 >= X1)) return;
       const int64_t idx = int64_t(i) * P.W + c0;
       if constexpr (U8OUT) {
@@ -459,6 +506,9 @@ struct InvWavePk {
       const int span = (64 * C1) >> (l - 1);
       hedge[l] = (j0 == 0) || (N - 1 >= j0 && N - 1 < j0 + span);
     }
+#pragma unroll
+    for (int l = 1; l <= L; ++l) voff[l] = 2u * uint32_t(c0 >> l);
+    own_col = c0 >= X0 && (last_win || c0 < X1);
     chk = 0;
 #pragma unroll
     for (int t = 0; t < R<1>; ++t) { Dp1[t] = 0; Xp1[t] = 0; }
@@ -528,15 +578,41 @@ __device__ __noinline__ void inv_wave_exact(const StageParams *P, int wave, cons
   x.run(wave);
 }
 
+// Whether the wavefront's lanes all read whole, aligned vectors from every
+// band row of every level and write whole output vectors (wave-uniform).
+template <int L, int C1, bool U8OUT>
+__device__ __forceinline__ bool wave_is_fast(const StageParams &P, int wave, int lane) {
+  const int win = wave % P.n_win;
+  const int cbase = (win == 0) ? 0 : win * P.own_w - P.halo_l;
+  const int c0 = cbase + lane * C1;
+  bool bad = !U8OUT || P.W % C1 != 0 || c0 + C1 > P.W;
+#pragma unroll
+  for (int l = 1; l <= L; ++l) {
+    const int uu = (C1 >> (l - 1)) / 2;
+    const int wl = P.wdim[l];
+    const int wh = P.wdim[l - 1] - wl;
+    const int bc = c0 >> l;
+    bad = bad || wl % uu != 0 || wh % uu != 0 || P.off_hl[l] % uu != 0 || P.off_lh[l] % uu != 0 ||
+          P.off_hh[l] % uu != 0 || wl - bc < uu || wh - bc < uu;
+  }
+  return __builtin_amdgcn_ballot_w64(bad) == 0;
+}
+
 // One wavefront's rectangle: the packed stream, redone with the 32-bit
 // stream when a value fell outside the packed range.
 template <int L, int C1, bool U8OUT>
 __device__ __forceinline__ void inv_wave(const StageParams &P, const StageParams *Pmem, int wave,
                                          const int16_t *llin, const int16_t *pub, void *out, int lane,
                                          uint32_t *ring, const uint32_t *te, const uint32_t *kw) {
-  InvWavePk<L, C1, U8OUT> w{P};
-  inv_setup(w, llin, pub, out, lane, ring, te, kw);
-  if (w.run(wave)) return;
+  if (wave_is_fast<L, C1, U8OUT>(P, wave, lane)) {
+    InvWavePk<L, C1, U8OUT, true> w{P};
+    inv_setup(w, llin, pub, out, lane, ring, te, kw);
+    if (w.run(wave)) return;
+  } else {
+    InvWavePk<L, C1, U8OUT, false> w{P};
+    inv_setup(w, llin, pub, out, lane, ring, te, kw);
+    if (w.run(wave)) return;
+  }
   wave_lds_sync();
   inv_wave_exact<L, C1, U8OUT>(Pmem, wave, llin, pub, out, lane, ring, te, kw);
 }
