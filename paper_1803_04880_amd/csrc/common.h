@@ -165,6 +165,19 @@ __device__ __forceinline__ int seg_start(const StageParams &P, int s) {
   return P.unit_rows * int((int64_t(s) * P.units) / P.n_seg);
 }
 
+// ------------------------------------------------------ global pointers --
+// Buffer accesses go through these: a pointer into device global memory, so
+// that loads and stores compile to global (not flat) instructions also where
+// the address was read from memory (batch items), which the compiler cannot
+// place in an address space by itself.  Cast with glob() first, then change
+// the pointee type.
+template <class T> using gptr = __attribute__((address_space(1))) T *;
+template <class T> __device__ __forceinline__ gptr<T> glob(T *p) { return (gptr<T>)p; }
+// 8- and 16-byte vectors for those accesses (plain vector types, which can be
+// read from any address space).
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 // ------------------------------------------------------- wavefront taps --
 // wave_shl:1 -> lane i receives lane i+1; wave_shr:1 -> lane i receives
 // lane i-1 (the lane with no source receives 0).

@@ -103,13 +103,13 @@ struct FwdWave {
   template <int Mv>
   __device__ __forceinline__ void store_band(int16_t *row, int bc, int nvalid, const uint32_t *V) {
     if (nvalid <= 0) return;
-    int16_t *dst = reinterpret_cast<int16_t *>(reinterpret_cast<char *>(row) + 2u * uint32_t(bc));
+    gptr<int16_t> dst = glob(row) + bc;
     const bool aligned = (reinterpret_cast<uintptr_t>(row) & (2 * Mv - 1)) == 0;
     if (nvalid >= Mv && aligned) {
       if constexpr (Mv == 1) *dst = int16_t(V[0]);
-      else if constexpr (Mv == 2) *reinterpret_cast<uint32_t *>(dst) = V[0];
-      else if constexpr (Mv == 4) *reinterpret_cast<uint2 *>(dst) = make_uint2(V[0], V[1]);
-      else *reinterpret_cast<uint4 *>(dst) = make_uint4(V[0], V[1], V[2], V[3]);
+      else if constexpr (Mv == 2) *(gptr<uint32_t>)dst = V[0];
+      else if constexpr (Mv == 4) *(gptr<u32x2>)dst = u32x2{V[0], V[1]};
+      else *(gptr<u32x4>)dst = u32x4{V[0], V[1], V[2], V[3]};
       return;
     }
 #pragma unroll
@@ -119,10 +119,11 @@ struct FwdWave {
 
   // Mv int16 values at an aligned address (Mv-element vector).
   template <int Mv> __device__ __forceinline__ static void store_vec(char *p, const uint32_t *V) {
-    if constexpr (Mv == 1) *reinterpret_cast<int16_t *>(p) = int16_t(V[0]);
-    else if constexpr (Mv == 2) *reinterpret_cast<uint32_t *>(p) = V[0];
-    else if constexpr (Mv == 4) *reinterpret_cast<uint2 *>(p) = make_uint2(V[0], V[1]);
-    else *reinterpret_cast<uint4 *>(p) = make_uint4(V[0], V[1], V[2], V[3]);
+    const gptr<char> g = glob(p);
+    if constexpr (Mv == 1) *(gptr<int16_t>)g = int16_t(V[0]);
+    else if constexpr (Mv == 2) *(gptr<uint32_t>)g = V[0];
+    else if constexpr (Mv == 4) *(gptr<u32x2>)g = u32x2{V[0], V[1]};
+    else *(gptr<u32x4>)g = u32x4{V[0], V[1], V[2], V[3]};
   }
 
   // Low row k of level l: lows -> LL_l (next level's queue / LL output),
@@ -393,10 +394,10 @@ struct FwdWave {
 #pragma unroll
     for (int q = 0; q < RW; q += (RW >= 4 ? 4 : 2)) {
       if constexpr (RW >= 4) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(src + off + 4u * q);
+        const u32x4 v = *(gptr<const u32x4>)(glob(src) + off + 4u * q);
         w[q] = v.x; w[q + 1] = v.y; w[q + 2] = v.z; w[q + 3] = v.w;
       } else {
-        const uint2 v = *reinterpret_cast<const uint2 *>(src + off + 4u * q);
+        const u32x2 v = *(gptr<const u32x2>)(glob(src) + off + 4u * q);
         w[q] = v.x; w[q + 1] = v.y;
       }
     }
@@ -410,8 +411,8 @@ struct FwdWave {
     for (int t = 0; t < C1; ++t) {
       const int c = c0 + t;
       if (c < G.W && rowbase + c < G.n_valid) {
-        if constexpr (U8IN) w[t >> 2] |= uint32_t(in8[rowbase + c]) << (8 * (t & 3));
-        else w[t >> 1] |= uint32_t(uint16_t(in16[rowbase + c])) << (16 * (t & 1));
+        if constexpr (U8IN) w[t >> 2] |= uint32_t(glob(in8)[rowbase + c]) << (8 * (t & 3));
+        else w[t >> 1] |= uint32_t(uint16_t(glob(in16)[rowbase + c])) << (16 * (t & 1));
       }
     }
   }

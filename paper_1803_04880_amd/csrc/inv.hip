@@ -102,12 +102,12 @@ struct InvWave {
           for (int q = 0; q < C1 / 4; ++q)
             w[q] = (uint32_t(x[4 * q]) & 0xFFu) | ((uint32_t(x[4 * q + 1]) & 0xFFu) << 8) |
                    ((uint32_t(x[4 * q + 2]) & 0xFFu) << 16) | (uint32_t(x[4 * q + 3]) << 24);
-          if constexpr (C1 == 8) *reinterpret_cast<uint2 *>(out8 + idx) = make_uint2(w[0], w[1]);
-          else *reinterpret_cast<uint4 *>(out8 + idx) = make_uint4(w[0], w[1], w[2], w[3]);
+          if constexpr (C1 == 8) *(gptr<u32x2>)(glob(out8) + idx) = u32x2{w[0], w[1]};
+          else *(gptr<u32x4>)(glob(out8) + idx) = u32x4{w[0], w[1], w[2], w[3]};
         } else {
 #pragma unroll
           for (int t = 0; t < C1; ++t)
-            if (t < lim) out8[idx + t] = uint8_t(x[t]);
+            if (t < lim) glob(out8)[idx + t] = uint8_t(x[t]);
         }
       } else {
         store_i16<C1>(out16, idx, P.W - c0, x);
@@ -315,16 +315,16 @@ struct InvWavePk {
   // UU int16 values at (row + off), UU-aligned: one vector load.
   template <int UU> __device__ __forceinline__ static void load_vec(const char *row, uint32_t off,
                                                                      uint32_t (&w)[Raw<UU>::W]) {
-    const char *p = row + off;
+    const gptr<const char> p = glob(row) + off;
     if constexpr (UU == 1) {
-      w[0] = *reinterpret_cast<const uint16_t *>(p);
+      w[0] = *(gptr<const uint16_t>)p;
     } else if constexpr (UU == 2) {
-      w[0] = *reinterpret_cast<const uint32_t *>(p);
+      w[0] = *(gptr<const uint32_t>)p;
     } else if constexpr (UU == 4) {
-      const uint2 q = *reinterpret_cast<const uint2 *>(p);
+      const u32x2 q = *(gptr<const u32x2>)p;
       w[0] = q.x; w[1] = q.y;
     } else {
-      const uint4 q = *reinterpret_cast<const uint4 *>(p);
+      const u32x4 q = *(gptr<const u32x4>)p;
       w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
     }
   }
@@ -376,10 +376,10 @@ struct InvWavePk {
           uint32_t w[C1 / 4];
 #pragma unroll
           for (int q = 0; q < C1 / 4; ++q) w[q] = __builtin_amdgcn_perm(O[q], E[q], 0x06020400u);
-          char *row = reinterpret_cast<char *>(out8) + int64_t(i) * P.W;
+          const gptr<uint8_t> row = glob(out8) + int64_t(i) * P.W;
           if (own_col) {
-            if constexpr (C1 == 8) *reinterpret_cast<uint2 *>(row + uint32_t(c0)) = make_uint2(w[0], w[1]);
-            else *reinterpret_cast<uint4 *>(row + uint32_t(c0)) = make_uint4(w[0], w[1], w[2], w[3]);
+            if constexpr (C1 == 8) *(gptr<u32x2>)(row + uint32_t(c0)) = u32x2{w[0], w[1]};
+            else *(gptr<u32x4>)(row + uint32_t(c0)) = u32x4{w[0], w[1], w[2], w[3]};
           }
           return;
         }
@@ -393,12 +393,12 @@ struct InvWavePk {
 #pragma unroll
         for (int q = 0; q < C1 / 4; ++q) w[q] = __builtin_amdgcn_perm(O[q], E[q], 0x06020400u);
         if (lim >= C1 && (idx & (C1 - 1)) == 0) {
-          if constexpr (C1 == 8) *reinterpret_cast<uint2 *>(out8 + idx) = make_uint2(w[0], w[1]);
-          else *reinterpret_cast<uint4 *>(out8 + idx) = make_uint4(w[0], w[1], w[2], w[3]);
+          if constexpr (C1 == 8) *(gptr<u32x2>)(glob(out8) + idx) = u32x2{w[0], w[1]};
+          else *(gptr<u32x4>)(glob(out8) + idx) = u32x4{w[0], w[1], w[2], w[3]};
         } else {
 #pragma unroll
           for (int t = 0; t < C1; ++t)
-            if (t < lim) out8[idx + t] = uint8_t(w[t >> 2] >> (8 * (t & 3)));
+            if (t < lim) glob(out8)[idx + t] = uint8_t(w[t >> 2] >> (8 * (t & 3)));
         }
       } else {
         uint32_t w[C1 / 2];
@@ -411,12 +411,12 @@ struct InvWavePk {
         if (lim >= C1 && (idx & (C1 - 1)) == 0) {
 #pragma unroll
           for (int q = 0; q < C1 / 8; ++q)
-            reinterpret_cast<uint4 *>(out16 + idx)[q] =
-                make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+            ((gptr<u32x4>)(glob(out16) + idx))[q] =
+                u32x4{w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
         } else {
 #pragma unroll
           for (int t = 0; t < C1; ++t)
-            if (t < lim) out16[idx + t] = int16_t(uint16_t(w[t >> 1] >> (16 * (t & 1))));
+            if (t < lim) glob(out16)[idx + t] = int16_t(uint16_t(w[t >> 1] >> (16 * (t & 1))));
         }
       }
     }
@@ -599,8 +599,10 @@ __device__ __forceinline__ bool wave_is_fast(const StageParams &P, int wave, int
 }
 
 // One wavefront's rectangle: the packed stream, redone with the 32-bit
-// stream when a value fell outside the packed range.
-template <int L, int C1, bool U8OUT>
+// stream when a value fell outside the packed range.  INLINE: the 32-bit
+// stream inlined rather than called (the persistent batch kernels run
+// markedly slower with a call in their tile loop, even one never taken).
+template <int L, int C1, bool U8OUT, bool INLINE = false>
 __device__ __forceinline__ void inv_wave(const StageParams &P, const StageParams *Pmem, int wave,
                                          const int16_t *llin, const int16_t *pub, void *out, int lane,
                                          uint32_t *ring, const uint32_t *te, const uint32_t *kw) {
@@ -614,7 +616,13 @@ __device__ __forceinline__ void inv_wave(const StageParams &P, const StageParams
     if (w.run(wave)) return;
   }
   wave_lds_sync();
-  inv_wave_exact<L, C1, U8OUT>(Pmem, wave, llin, pub, out, lane, ring, te, kw);
+  if constexpr (INLINE) {
+    InvWave<L, C1, U8OUT> x{P};
+    inv_setup(x, llin, pub, out, lane, ring, te, kw);
+    x.run(wave);
+  } else {
+    inv_wave_exact<L, C1, U8OUT>(Pmem, wave, llin, pub, out, lane, ring, te, kw);
+  }
 }
 
 template <int L, int C1, bool U8OUT>
@@ -712,8 +720,8 @@ __device__ __forceinline__ void inv_batch_body(const BatchItem *__restrict__ ite
       s_kw[wib][lane] = v;
     }
     wave_lds_sync();
-    inv_wave<L, C1, true>(it.inv, &it.inv, e.y, reinterpret_cast<const int16_t *>(it.priv), it.pub, it.out, lane,
-                          s_ring[wib], s_te, s_kw[wib]);
+    inv_wave<L, C1, true, true>(it.inv, &it.inv, e.y, reinterpret_cast<const int16_t *>(it.priv), it.pub,
+                                it.out, lane, s_ring[wib], s_te, s_kw[wib]);
     wave_lds_sync();
   }
 }

@@ -89,22 +89,22 @@ __device__ __forceinline__ void store_i16(int16_t *base, int64_t idx, int nvalid
     for (int i = 0; i < U / 2; ++i)
       w[i] = (uint32_t(v[2 * i]) & 0xFFFFu) | (uint32_t(v[2 * i + 1]) << 16);
     if constexpr (U == 2) {
-      *reinterpret_cast<uint32_t *>(base + idx) = w[0];
+      *(gptr<uint32_t>)(glob(base) + idx) = w[0];
     } else if constexpr (U == 4) {
-      *reinterpret_cast<uint2 *>(base + idx) = make_uint2(w[0], w[1]);
+      *(gptr<u32x2>)(glob(base) + idx) = u32x2{w[0], w[1]};
     } else if constexpr (U == 8) {
-      *reinterpret_cast<uint4 *>(base + idx) = make_uint4(w[0], w[1], w[2], w[3]);
+      *(gptr<u32x4>)(glob(base) + idx) = u32x4{w[0], w[1], w[2], w[3]};
     } else {
 #pragma unroll
       for (int i = 0; i < U / 8; ++i)
-        reinterpret_cast<uint4 *>(base + idx)[i] =
-            make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
+        ((gptr<u32x4>)(glob(base) + idx))[i] =
+            u32x4{w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]};
     }
     return;
   }
 #pragma unroll
   for (int u = 0; u < U; ++u)
-    if (u < nvalid) base[idx + u] = int16_t(v[u]);
+    if (u < nvalid) glob(base)[idx + u] = int16_t(v[u]);
 }
 
 template <int U>
@@ -112,17 +112,17 @@ __device__ __forceinline__ void load_i16(const int16_t *base, int64_t idx, int n
   if (U >= 2 && nvalid >= U && (idx & (U - 1)) == 0) {
     uint32_t w[U / 2 > 0 ? U / 2 : 1];
     if constexpr (U == 2) {
-      w[0] = *reinterpret_cast<const uint32_t *>(base + idx);
+      w[0] = *(gptr<const uint32_t>)(glob(base) + idx);
     } else if constexpr (U == 4) {
-      uint2 q = *reinterpret_cast<const uint2 *>(base + idx);
+      u32x2 q = *(gptr<const u32x2>)(glob(base) + idx);
       w[0] = q.x; w[1] = q.y;
     } else if constexpr (U == 8) {
-      uint4 q = *reinterpret_cast<const uint4 *>(base + idx);
+      u32x4 q = *(gptr<const u32x4>)(glob(base) + idx);
       w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
     } else {
 #pragma unroll
       for (int i = 0; i < U / 8; ++i) {
-        uint4 q = reinterpret_cast<const uint4 *>(base + idx)[i];
+        u32x4 q = ((gptr<const u32x4>)(glob(base) + idx))[i];
         w[4 * i] = q.x; w[4 * i + 1] = q.y; w[4 * i + 2] = q.z; w[4 * i + 3] = q.w;
       }
     }
@@ -134,7 +134,7 @@ __device__ __forceinline__ void load_i16(const int16_t *base, int64_t idx, int n
     return;
   }
 #pragma unroll
-  for (int u = 0; u < U; ++u) v[u] = (u < nvalid) ? int(base[idx + u]) : 0;
+  for (int u = 0; u < U; ++u) v[u] = (u < nvalid) ? int(glob(base)[idx + u]) : 0;
 }
 
 // Raw form: U int16 values as W = max(1, U/2) packed words (value u in the
@@ -146,14 +146,14 @@ __device__ __forceinline__ void load_raw(const int16_t *base, int64_t idx, int n
                                          uint32_t (&w)[Raw<U>::W]) {
   if (U >= 2 && nvalid >= U && (idx & (U - 1)) == 0) {
     if constexpr (U == 2) {
-      w[0] = *reinterpret_cast<const uint32_t *>(base + idx);
+      w[0] = *(gptr<const uint32_t>)(glob(base) + idx);
     } else if constexpr (U == 4) {
-      const uint2 q = *reinterpret_cast<const uint2 *>(base + idx);
+      const u32x2 q = *(gptr<const u32x2>)(glob(base) + idx);
       w[0] = q.x; w[1] = q.y;
     } else {
 #pragma unroll
       for (int i = 0; i < U / 8; ++i) {
-        const uint4 q = reinterpret_cast<const uint4 *>(base + idx)[i];
+        const u32x4 q = ((gptr<const u32x4>)(glob(base) + idx))[i];
         w[4 * i] = q.x; w[4 * i + 1] = q.y; w[4 * i + 2] = q.z; w[4 * i + 3] = q.w;
       }
     }
@@ -163,7 +163,7 @@ __device__ __forceinline__ void load_raw(const int16_t *base, int64_t idx, int n
   for (int i = 0; i < Raw<U>::W; ++i) w[i] = 0;
 #pragma unroll
   for (int u = 0; u < U; ++u)
-    if (u < nvalid) w[u >> 1] |= uint32_t(uint16_t(base[idx + u])) << (16 * (u & 1));
+    if (u < nvalid) w[u >> 1] |= uint32_t(uint16_t(glob(base)[idx + u])) << (16 * (u & 1));
 }
 
 template <int U>
