@@ -566,18 +566,6 @@ __device__ __forceinline__ void inv_setup(Wv &w, const int16_t *llin, const int1
   w.ks.blocks = w.P.ks_blocks;
 }
 
-// The 32-bit stream as a function of its own: kept out of line so that its
-// registers do not add to the packed stream's; it reads the plan through a
-// pointer (a copy in LDS, or the batch item in device memory).
-template <int L, int C1, bool U8OUT>
-__device__ __noinline__ void inv_wave_exact(const StageParams *P, int wave, const int16_t *llin,
-                                            const int16_t *pub, void *out, int lane, uint32_t *ring,
-                                            const uint32_t *te, const uint32_t *kw) {
-  InvWave<L, C1, U8OUT> x{*P};
-  inv_setup(x, llin, pub, out, lane, ring, te, kw);
-  x.run(wave);
-}
-
 // Whether the wavefront's lanes all read whole, aligned vectors from every
 // band row of every level and write whole output vectors (wave-uniform).
 template <int L, int C1, bool U8OUT>
@@ -599,13 +587,11 @@ __device__ __forceinline__ bool wave_is_fast(const StageParams &P, int wave, int
 }
 
 // One wavefront's rectangle: the packed stream, redone with the 32-bit
-// stream when a value fell outside the packed range.  INLINE: the 32-bit
-// stream inlined rather than called (the persistent batch kernels run
-// markedly slower with a call in their tile loop, even one never taken).
-template <int L, int C1, bool U8OUT, bool INLINE = false>
-__device__ __forceinline__ void inv_wave(const StageParams &P, const StageParams *Pmem, int wave,
-                                         const int16_t *llin, const int16_t *pub, void *out, int lane,
-                                         uint32_t *ring, const uint32_t *te, const uint32_t *kw) {
+// stream when a value fell outside the packed range.
+template <int L, int C1, bool U8OUT>
+__device__ __forceinline__ void inv_wave(const StageParams &P, int wave, const int16_t *llin,
+                                         const int16_t *pub, void *out, int lane, uint32_t *ring,
+                                         const uint32_t *te, const uint32_t *kw) {
   if (wave_is_fast<L, C1, U8OUT>(P, wave, lane)) {
     InvWavePk<L, C1, U8OUT, true> w{P};
     inv_setup(w, llin, pub, out, lane, ring, te, kw);
@@ -616,13 +602,9 @@ __device__ __forceinline__ void inv_wave(const StageParams &P, const StageParams
     if (w.run(wave)) return;
   }
   wave_lds_sync();
-  if constexpr (INLINE) {
-    InvWave<L, C1, U8OUT> x{P};
-    inv_setup(x, llin, pub, out, lane, ring, te, kw);
-    x.run(wave);
-  } else {
-    inv_wave_exact<L, C1, U8OUT>(Pmem, wave, llin, pub, out, lane, ring, te, kw);
-  }
+  InvWave<L, C1, U8OUT> x{P};
+  inv_setup(x, llin, pub, out, lane, ring, te, kw);
+  x.run(wave);
 }
 
 template <int L, int C1, bool U8OUT>
@@ -632,19 +614,14 @@ __device__ __forceinline__ void inv_body(const int16_t *__restrict__ llin,
   __shared__ uint32_t s_te[1024];
   __shared__ uint32_t s_kw[kKeyWords];
   __shared__ uint32_t s_ring[kWavesPerBlock][kRingBlocks * 4];
-  __shared__ StageParams s_P;   // the plan as the exact stream reads it
-  static_assert(sizeof(StageParams) % 4 == 0, "plan copied as words");
   if (P.use_aes) load_aes_tables(s_te, s_kw, P.key);
-  for (int i = threadIdx.x; i < int(sizeof(StageParams) / 4); i += blockDim.x)
-    reinterpret_cast<uint32_t *>(&s_P)[i] = reinterpret_cast<const uint32_t *>(&P)[i];
   __syncthreads();
   // the wavefront index is uniform; readfirstlane lets the compiler see that,
   // so all row / level bookkeeping derived from it stays scalar
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wave = blockIdx.x * kWavesPerBlock + wib;
   if (wave >= P.n_waves) return;
-  inv_wave<L, C1, U8OUT>(P, &s_P, wave, llin, pub, out, int(threadIdx.x & 63), s_ring[wib], s_te,
-                         s_kw);
+  inv_wave<L, C1, U8OUT>(P, wave, llin, pub, out, int(threadIdx.x & 63), s_ring[wib], s_te, s_kw);
 }
 
 // Eight columns per lane: held to 128 VGPRs (four wavefronts per SIMD), the
@@ -657,7 +634,7 @@ void inv_kernel8(const int16_t *__restrict__ llin, const int16_t *__restrict__ p
 }
 
 // Sixteen columns per lane need more registers than that: two wavefronts
-// per SIMD (256 VGPRs, which also bounds the out-of-line exact stream).
+// per SIMD (256 VGPRs).
 template <int L, bool U8OUT>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2)))
 void inv_kernel16(const int16_t *__restrict__ llin, const int16_t *__restrict__ pub,
@@ -720,8 +697,8 @@ __device__ __forceinline__ void inv_batch_body(const BatchItem *__restrict__ ite
       s_kw[wib][lane] = v;
     }
     wave_lds_sync();
-    inv_wave<L, C1, true, true>(it.inv, &it.inv, e.y, reinterpret_cast<const int16_t *>(it.priv), it.pub,
-                                it.out, lane, s_ring[wib], s_te, s_kw[wib]);
+    inv_wave<L, C1, true>(it.inv, e.y, reinterpret_cast<const int16_t *>(it.priv), it.pub, it.out, lane,
+                          s_ring[wib], s_te, s_kw[wib]);
     wave_lds_sync();
   }
 }
