@@ -221,6 +221,21 @@ def main():
                 "avg_launch_us": round(dom_us, 2)}
     pair_roof = 2 * alg_bytes / (avg_p + avg_r) / 1e3 / HBM_PEAK_GBS
 
+    # context for the HBM fraction: the rate of a plain device copy of the
+    # same n bytes (read n, write n) on this GPU, timed the same way
+    spare = torch.empty_like(x)
+    spare.copy_(x)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(20):
+        spare.copy_(x)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_us = c0.elapsed_time(c1) * 1e3 / 20
+    del spare
+    device_copy = {"us": round(copy_us, 1), "gbps": round(2 * n / (copy_us * 1e-6) / 1e9, 1),
+                   "dominant_kernel_frac_of_copy": round(achieved / (2 * n / (copy_us * 1e-6) / 1e9), 4)}
+
     cold = None
     if args.cold:
         scratch = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
@@ -264,6 +279,7 @@ def main():
                        "pair_p99": round(percentile(t_pair, 99), 1)},
         "roofline": roofline,
         "pair_hbm_frac": round(pair_roof, 4),
+        "device_copy": device_copy,
         "cold": cold,
         "cpu_baseline": None,
     }
