@@ -462,17 +462,30 @@ struct InvWavePk {
       last_pair = (2 * k + 1 == N - 1);  // even length: row 2k+1 = d + x(2k)
       if (k != k0[l]) e_begin = 0;
     }
-    const int e_end = last_pair ? 3 : 2;
-    // one call site per level: the rows go through a loop
-#pragma unroll 1
-    for (int e = e_begin; e < e_end; ++e) {
-      uint32_t row[Rl];
-#pragma unroll
-      for (int t = 0; t < Rl; ++t) row[t] = (e & 1) ? Rb[t] : Ra[t];
-      emit_row<l>(row, 2 * k - 1 + e);
-      if (e == 1 && last_pair) {
+    if constexpr (l == 1) {
+      // level-1 rows end in stores, not in further levels: a call site per
+      // row costs little code and needs no row selects
+      if (e_begin == 0) emit_row<1>(Ra, 2 * k - 1);
+      emit_row<1>(Rb, 2 * k);
+      if (last_pair) {
 #pragma unroll
         for (int t = 0; t < Rl; ++t) Ra[t] = pk_add(Dv[t], Xv[t]);
+        emit_row<1>(Ra, 2 * k + 1);
+      }
+    } else {
+      const int e_end = last_pair ? 3 : 2;
+      // one call site per level (each inlines the finer levels): the rows
+      // go through a loop
+#pragma unroll 1
+      for (int e = e_begin; e < e_end; ++e) {
+        uint32_t row[Rl];
+#pragma unroll
+        for (int t = 0; t < Rl; ++t) row[t] = (e & 1) ? Rb[t] : Ra[t];
+        emit_row<l>(row, 2 * k - 1 + e);
+        if (e == 1 && last_pair) {
+#pragma unroll
+          for (int t = 0; t < Rl; ++t) Ra[t] = pk_add(Dv[t], Xv[t]);
+        }
       }
     }
   }

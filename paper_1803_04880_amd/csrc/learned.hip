@@ -127,17 +127,27 @@ __device__ __forceinline__ int correction_mfma(const MfmaNet &m, const int (&e)[
 #pragma unroll
   for (int j = 0; j < kCtx; ++j) c[j] = clamp_i(e[j] - base, -128, 127);
   const long b = long(pack4(c[0], c[1], c[2], c[3])) | (long(pack4(c[4], c[5], c[6], c[7])) << 32);
-  int mine = 0;
+  // p[g]: this lane's quarter of the output sum of group g's sample l % 16
+  // (its four hidden units 4q..4q+3, q = l / 16)
+  int p[4];
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
     const v4i d = __builtin_amdgcn_mfma_i32_16x16x32_i8(m.a[g], b, m.bias, 0, 0, 0);
     int sum = 0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) sum += clamp_i(d[r], 0, 0x7fffff) * m.w2[r];
-    sum += __shfl_xor(sum, 16);
-    sum += __shfl_xor(sum, 32);
-    if ((lane >> 4) == g) mine = sum;
+    p[g] = sum;
   }
+  // Lane l needs group q's total: the sum of p[q] over lanes s, s+16, s+32,
+  // s+48 (s = l % 16).  Two exchange rounds: across lane halves (q ^ 2) each
+  // lane keeps the pair of groups {2(q/2), 2(q/2)+1} and sends the other
+  // pair; then across q ^ 1 it keeps group q and sends the other.
+  const int q = lane >> 4;
+  const bool hi = (q & 2) != 0;
+  const int k0 = (hi ? p[2] : p[0]) + __shfl_xor(hi ? p[0] : p[2], 32);
+  const int k1 = (hi ? p[3] : p[1]) + __shfl_xor(hi ? p[1] : p[3], 32);
+  const bool odd = (q & 1) != 0;
+  const int mine = (odd ? k1 : k0) + __shfl_xor(odd ? k0 : k1, 16);
   return clamp_i((mine + m.b2) >> m.shift, -255, 255);
 }
 
