@@ -44,7 +44,7 @@ def percentile(xs, q):
 
 
 # sources of the kernels and launch planning the plain protect / restore runs
-PLAIN_PATH_SOURCES = ("api.hip", "common.h", "ctr.hip", "fwd.hip", "inv.hip", "lift.h", "pack.h")
+PLAIN_PATH_SOURCES = ("api.hip", "common.h", "fwd.hip", "inv.hip", "lift.h", "pack.h")
 
 
 def source_hash() -> str:

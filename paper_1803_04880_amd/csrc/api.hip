@@ -278,8 +278,6 @@ int dwtfrag_protect(const uint8_t *in, uint64_t n, uint32_t width, uint32_t leve
     if (launch_fwd(Ls[s], C1s[s], s == 0, src, pub, dst, plans[s], st) != hipSuccess)
       return DWTFRAG_EDEVICE;
   }
-  // the last stage left LL_L in clear in priv: encrypt it in place
-  if (launch_ctr(priv, priv, g.priv_bytes, k, 0, st) != hipSuccess) return DWTFRAG_EDEVICE;
   return DWTFRAG_OK;
 }
 

@@ -21,8 +21,6 @@ struct BatchItem {
   int16_t *pub;        // public fragment (device)
   uint8_t *out;        // restore output (device)
   uint64_t priv_bytes; // 2 * h_L * w_L
-  uint64_t aes_blocks; // 16-byte blocks of priv
-  uint64_t aes_first;  // blocks of the items before this one (prefix sum)
 };
 
 // Tile queue head counters, reset by a kernel before every drain: one per

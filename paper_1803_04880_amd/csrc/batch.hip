@@ -5,9 +5,9 @@
 // host (every item's geometry and launch plan, grouped into classes of equal
 // kernel shape, with one tile list per class), copied into a caller-owned
 // device buffer, and then run by persistent launches that drain each class's
-// tile queue: protect = forward drains + one counter-mode pass over every
-// item's private fragment; restore = inverse drains (decryption fused).  The
-// run calls launch kernels only, so they can be captured in a HIP graph.
+// tile queue: protect = forward drains (encryption fused), restore = inverse
+// drains (decryption fused).  The run calls launch kernels only, so they can
+// be captured in a HIP graph.
 #include "dwtfrag.h"
 
 #include <algorithm>
@@ -24,7 +24,6 @@ hipError_t launch_fwd_batch(int L, int C1, const BatchItem *items, const int2 *t
                             unsigned int *head, int blocks, hipStream_t s);
 hipError_t launch_inv_batch(int L, int C1, const BatchItem *items, const int2 *tiles, int64_t n_tiles,
                             unsigned int *head, int blocks, hipStream_t s);
-hipError_t launch_ctr_batch(const BatchItem *items, int count, uint64_t total_blocks, hipStream_t s);
 int fwd_waves_per_cu(int L, int C1, bool u8in);
 int inv_waves_per_cu(int L, int C1, bool u8out);
 int plan_single_stage(uint64_t n, uint32_t width, uint32_t levels, bool forward,
@@ -46,7 +45,6 @@ struct dwtfrag_batch {
   std::vector<int2> tiles;                 // forward classes, then inverse classes
   std::vector<BatchClass> fwd_cls, inv_cls;
   std::vector<int> fwd_blocks, inv_blocks; // persistent grid per class
-  uint64_t total_aes_blocks = 0;
   uint64_t off_items = 0, off_tiles = 0, off_heads = 0, bytes = 0;
   char *dev = nullptr;                     // caller's device copy, set by upload
 };
@@ -130,9 +128,6 @@ int dwtfrag_batch_create(const dwtfrag_item *items, uint32_t count, const dwtfra
     bi.pub = src.pub;
     bi.out = src.out;
     bi.priv_bytes = priv_bytes;
-    bi.aes_blocks = (priv_bytes + 15) / 16;
-    bi.aes_first = b->total_aes_blocks;
-    b->total_aes_blocks += bi.aes_blocks;
     const int cf = class_index(b->fwd_cls, Lf, Cf);
     const int ci = class_index(b->inv_cls, Li, Ci);
     if (int(b->fwd_cls.size()) > kBatchClasses || int(b->inv_cls.size()) > kBatchClasses) {
@@ -219,8 +214,6 @@ int dwtfrag_batch_protect(const dwtfrag_batch *b, void *stream) {
     if (launch_fwd_batch(k.L, k.C1, items, tiles + k.tile_off, k.n_tiles, heads + c, blocks, st) != hipSuccess)
       return DWTFRAG_EDEVICE;
   }
-  if (launch_ctr_batch(items, int(b->count), b->total_aes_blocks, st) != hipSuccess)
-    return DWTFRAG_EDEVICE;
   return DWTFRAG_OK;
 }
 

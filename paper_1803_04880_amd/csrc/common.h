@@ -121,21 +121,28 @@ static __constant__ AesTables c_aes = make_aes_tables();
 
 // Fill the four rotated tables (1024 words) and the key words cooperatively;
 // the caller synchronises the block afterwards.
-__device__ __forceinline__ void load_aes_tables(uint32_t *te, uint32_t *kw, const AesKey &key) {
+// The four byte-rotated T-tables into LDS, loaded by the whole block.
+__device__ __forceinline__ void load_aes_te(uint32_t *te) {
   for (int i = threadIdx.x; i < 1024; i += blockDim.x) {
     const uint32_t v = c_aes.te0[i & 255];
     const int r = 8 * (i >> 8);
     te[i] = r ? ((v << r) | (v >> (32 - r))) : v;
   }
-  for (int i = threadIdx.x; i < kKeyWords; i += blockDim.x) {
-    uint32_t v;
-    if (i < 44) v = key.rk[i];
-    else if (i == 44) v = uint32_t(key.nonce_hi);
-    else if (i == 45) v = uint32_t(key.nonce_hi >> 32);
-    else if (i == 46) v = uint32_t(key.nonce_lo);
-    else v = uint32_t(key.nonce_lo >> 32);
-    kw[i] = v;
-  }
+}
+
+// Word i (< kKeyWords) of the LDS key block: 44 round-key words, then the
+// nonce's two 64-bit halves as low / high words.
+__device__ __forceinline__ uint32_t key_word(const AesKey &key, int i) {
+  if (i < 44) return key.rk[i];
+  if (i == 44) return uint32_t(key.nonce_hi);
+  if (i == 45) return uint32_t(key.nonce_hi >> 32);
+  if (i == 46) return uint32_t(key.nonce_lo);
+  return uint32_t(key.nonce_lo >> 32);
+}
+
+__device__ __forceinline__ void load_aes_tables(uint32_t *te, uint32_t *kw, const AesKey &key) {
+  load_aes_te(te);
+  for (int i = threadIdx.x; i < kKeyWords; i += blockDim.x) kw[i] = key_word(key, i);
 }
 
 // --------------------------------------------------------- launch geometry --

@@ -1,7 +1,8 @@
-// Forward path: fused multi-level 5/3 lifting with band scatter, as one
-// streaming kernel.  The last LL band is written in clear to the private
-// fragment's buffer and encrypted in place by the counter-mode kernel
-// (ctr.hip) launched right after.
+// Forward path: fused multi-level 5/3 lifting with band scatter and the
+// counter-mode encryption of the last LL band, as one streaming kernel.  A
+// wavefront writes its owned LL rectangle in clear while it streams, then
+// encrypts it in place once its stream has ended (so the AES rounds do not
+// share registers with the stream).
 //
 // Ch. 5 section 5.1.1: each level runs the horizontal pass (eqs. (5.1)-(5.2)
 // along rows), then the vertical pass, and the next level transforms LL only.
@@ -46,6 +47,8 @@ struct FwdWave {
   int16_t *pub;
   int16_t *llout;
   uint32_t *lds;          // this wavefront's staging rows, then the level queues
+  const uint32_t *te;     // AES tables in LDS (use_aes)
+  const uint32_t *kw;     // round keys + nonce in LDS
   int lane;
   int c0;                 // level-0 column of this lane's first sample
   int X0, Y0, X1, Y1;     // owned rectangle (level 0), X1 / Y1 exclusive
@@ -557,6 +560,51 @@ struct FwdWave {
       }
       fast_cur = fast_next;
     }
+    if (G.use_aes) encrypt_owned();
+  }
+
+  // AES-128-CTR over this wavefront's owned LL_L rectangle, in place: the
+  // keystream is indexed by the byte offset in the LL band, so each 16-byte
+  // block is computed where needed and only the owned elements are XORed
+  // (blocks shared with a neighbour's rectangle are computed by both; each
+  // writes its own bytes).
+  __device__ __forceinline__ void encrypt_owned() {
+    const int kr0 = Y0 >> L;
+    const int kr1 = last_seg ? G.hdim[L] : min(G.hdim[L], Y1 >> L);
+    const int cc0 = min(G.wdim[L], X0 >> L);
+    const int cc1 = last_win ? G.wdim[L] : min(G.wdim[L], X1 >> L);
+    if (kr0 >= kr1 || cc0 >= cc1) return;
+    // this wavefront's clear LL stores complete before it reads them back
+    // (the same compute unit; no other wavefront touches these elements)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    const int64_t wL = G.wdim[L];
+    const int nb = ((2 * (cc1 - cc0) + 30) >> 4) + 1;  // blocks a row can touch
+    const int total = (kr1 - kr0) * nb;
+    const gptr<uint16_t> ll = glob(reinterpret_cast<uint16_t *>(llout));
+    for (int i = lane; i < total; i += 64) {
+      const int r = kr0 + i / nb;
+      const int64_t e0 = int64_t(r) * wL + cc0, e1 = int64_t(r) * wL + cc1;  // elements [e0, e1)
+      const int64_t b = ((2 * e0) >> 4) + (i % nb);
+      if (b > ((2 * e1 - 1) >> 4)) continue;
+      uint32_t w[4];
+      counter_block(kw, uint64_t(b), w);
+      aes_encrypt(te, kw, w);
+      // a block wholly inside the owned run is read and written as 16
+      // bytes; one at an edge element by element, owned elements only, so a
+      // neighbour's bytes and any bytes past the band's end are not touched
+      if (8 * b >= e0 && 8 * b + 8 <= e1) {
+        const gptr<u32x4> p = (gptr<u32x4>)(ll + 8 * b);
+        u32x4 v = *p;
+        v.x ^= w[0]; v.y ^= w[1]; v.z ^= w[2]; v.w ^= w[3];
+        *p = v;
+      } else {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int64_t e = 8 * b + t;
+          if (e >= e0 && e < e1) ll[e] ^= uint16_t(w[t >> 1] >> (16 * (t & 1)));
+        }
+      }
+    }
   }
 };
 
@@ -567,12 +615,18 @@ __global__ __launch_bounds__(kBlockThreads) void fwd_kernel(const void *__restri
                                                             const StageParams P) {
   using W = FwdWave<L, C1, U8IN>;
   __shared__ uint32_t s_lds[kWavesPerBlock][W::kLdsWords];
+  __shared__ uint32_t s_te[1024];
+  __shared__ uint32_t s_kw[kKeyWords];
+  if (P.use_aes) load_aes_tables(s_te, s_kw, P.key);
+  __syncthreads();
   // the wavefront index is uniform; readfirstlane lets the compiler see that,
   // so all row / level bookkeeping derived from it stays scalar
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wave = blockIdx.x * kWavesPerBlock + wib;
   if (wave >= P.n_waves) return;
   W w{P};
+  w.te = s_te;
+  w.kw = s_kw;
   w.in8 = static_cast<const uint8_t *>(in);
   w.in16 = static_cast<const int16_t *>(in);
   w.pub = pub;
@@ -600,6 +654,10 @@ __global__ __launch_bounds__(kBlockThreads) void fwd_batch_kernel(const BatchIte
                                                                   unsigned int *__restrict__ head) {
   using W = FwdWave<L, C1, true>;
   __shared__ uint32_t s_lds[kWavesPerBlock][W::kLdsWords];
+  __shared__ uint32_t s_te[1024];
+  __shared__ uint32_t s_kw[kWavesPerBlock][kKeyWords];
+  load_aes_te(s_te);
+  __syncthreads();
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   for (;;) {
@@ -609,7 +667,11 @@ __global__ __launch_bounds__(kBlockThreads) void fwd_batch_kernel(const BatchIte
     if (int64_t(t) >= n_tiles) break;
     const int2 e = tiles[t];
     const BatchItem &it = items[e.x];
+    if (lane < kKeyWords) s_kw[wib][lane] = key_word(it.fwd.key, lane);  // this item's keys
+    wave_lds_sync();
     W w{it.fwd};
+    w.te = s_te;
+    w.kw = s_kw[wib];
     w.in8 = it.in;
     w.in16 = nullptr;
     w.pub = it.pub;

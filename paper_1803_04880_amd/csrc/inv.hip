@@ -684,11 +684,7 @@ __device__ __forceinline__ void inv_batch_body(const BatchItem *__restrict__ ite
   __shared__ uint32_t s_te[1024];
   __shared__ uint32_t s_kw[kWavesPerBlock][kKeyWords];
   __shared__ uint32_t s_ring[kWavesPerBlock][kRingBlocks * 4];
-  for (int i = threadIdx.x; i < 1024; i += blockDim.x) {
-    const uint32_t v = c_aes.te0[i & 255];
-    const int r = 8 * (i >> 8);
-    s_te[i] = r ? ((v << r) | (v >> (32 - r))) : v;
-  }
+  load_aes_te(s_te);
   __syncthreads();
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -699,16 +695,7 @@ __device__ __forceinline__ void inv_batch_body(const BatchItem *__restrict__ ite
     if (int64_t(t) >= n_tiles) break;
     const int2 e = tiles[t];
     const BatchItem &it = items[e.x];
-    if (lane < kKeyWords) {
-      const AesKey &k = it.inv.key;
-      uint32_t v;
-      if (lane < 44) v = k.rk[lane];
-      else if (lane == 44) v = uint32_t(k.nonce_hi);
-      else if (lane == 45) v = uint32_t(k.nonce_hi >> 32);
-      else if (lane == 46) v = uint32_t(k.nonce_lo);
-      else v = uint32_t(k.nonce_lo >> 32);
-      s_kw[wib][lane] = v;
-    }
+    if (lane < kKeyWords) s_kw[wib][lane] = key_word(it.inv.key, lane);  // this item's keys
     wave_lds_sync();
     inv_wave<L, C1, true>(it.inv, e.y, reinterpret_cast<const int16_t *>(it.priv), it.pub, it.out, lane,
                           s_ring[wib], s_te, s_kw[wib]);
