@@ -119,9 +119,8 @@ __device__ __forceinline__ void aes_encrypt(const uint32_t *te, const uint32_t *
 
 static __constant__ AesTables c_aes = make_aes_tables();
 
-// Fill the four rotated tables (1024 words) and the key words cooperatively;
-// the caller synchronises the block afterwards.
-// The four byte-rotated T-tables into LDS, loaded by the whole block.
+// The four byte-rotated T-tables (1024 words) into LDS, loaded by the whole
+// block; the caller synchronises the block afterwards.
 __device__ __forceinline__ void load_aes_te(uint32_t *te) {
   for (int i = threadIdx.x; i < 1024; i += blockDim.x) {
     const uint32_t v = c_aes.te0[i & 255];
@@ -140,6 +139,7 @@ __device__ __forceinline__ uint32_t key_word(const AesKey &key, int i) {
   return uint32_t(key.nonce_lo >> 32);
 }
 
+// Tables and key words together, for a block that uses one key.
 __device__ __forceinline__ void load_aes_tables(uint32_t *te, uint32_t *kw, const AesKey &key) {
   load_aes_te(te);
   for (int i = threadIdx.x; i < kKeyWords; i += blockDim.x) kw[i] = key_word(key, i);

@@ -578,32 +578,51 @@ struct FwdWave {
     // (the same compute unit; no other wavefront touches these elements)
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     const int64_t wL = G.wdim[L];
+    const int64_t band = int64_t(G.hdim[L]) * wL;      // elements in the LL band
     const int nb = ((2 * (cc1 - cc0) + 30) >> 4) + 1;  // blocks a row can touch
     const int total = (kr1 - kr0) * nb;
     const gptr<uint16_t> ll = glob(reinterpret_cast<uint16_t *>(llout));
+    // lane work item i = (row kr0 + i / nb, block i % nb of that row); the
+    // pair is stepped by 64 items per pass instead of divided each time
+    const int step_r = 64 / nb, step_c = 64 % nb;
+    int r = kr0 + lane / nb, c = lane % nb;
     for (int i = lane; i < total; i += 64) {
-      const int r = kr0 + i / nb;
       const int64_t e0 = int64_t(r) * wL + cc0, e1 = int64_t(r) * wL + cc1;  // elements [e0, e1)
-      const int64_t b = ((2 * e0) >> 4) + (i % nb);
-      if (b > ((2 * e1 - 1) >> 4)) continue;
-      uint32_t w[4];
-      counter_block(kw, uint64_t(b), w);
-      aes_encrypt(te, kw, w);
-      // a block wholly inside the owned run is read and written as 16
-      // bytes; one at an edge element by element, owned elements only, so a
-      // neighbour's bytes and any bytes past the band's end are not touched
-      if (8 * b >= e0 && 8 * b + 8 <= e1) {
+      const int64_t b = ((2 * e0) >> 4) + c;
+      if (b <= ((2 * e1 - 1) >> 4)) {
+        uint32_t w[4];
+        counter_block(kw, uint64_t(b), w);
+        aes_encrypt(te, kw, w);
         const gptr<u32x4> p = (gptr<u32x4>)(ll + 8 * b);
-        u32x4 v = *p;
-        v.x ^= w[0]; v.y ^= w[1]; v.z ^= w[2]; v.w ^= w[3];
-        *p = v;
-      } else {
+        if (8 * b + 8 <= band) {
+          // the block lies in the band: one 16-byte read; written back whole
+          // when all of it is owned, else only the owned elements (bytes of
+          // a neighbour's rectangle read with them are discarded, never
+          // written)
+          u32x4 v = *p;
+          v.x ^= w[0]; v.y ^= w[1]; v.z ^= w[2]; v.w ^= w[3];
+          if (8 * b >= e0 && 8 * b + 8 <= e1) {
+            *p = v;
+          } else {
+            const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int64_t e = 8 * b + t;
-          if (e >= e0 && e < e1) ll[e] ^= uint16_t(w[t >> 1] >> (16 * (t & 1)));
+            for (int t = 0; t < 8; ++t) {
+              const int64_t e = 8 * b + t;
+              if (e >= e0 && e < e1) ll[e] = uint16_t(vw[t >> 1] >> (16 * (t & 1)));
+            }
+          }
+        } else {
+          // the band's last block runs past its end: element by element
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int64_t e = 8 * b + t;
+            if (e >= e0 && e < e1) ll[e] ^= uint16_t(w[t >> 1] >> (16 * (t & 1)));
+          }
         }
       }
+      c += step_c;
+      r += step_r;
+      if (c >= nb) { c -= nb; ++r; }
     }
   }
 };

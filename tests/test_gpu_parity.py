@@ -72,6 +72,22 @@ def test_protect_matches_oracle_and_roundtrips(n, width, levels):
     assert back == buf.tobytes()
 
 
+@pytest.mark.parametrize("nonce_hex", ["0011223344556677ffffffffffffff9c", "ffffffffffffffffffffffffffffff9c"])
+def test_protect_counter_carries_match_oracle(nonce_hex):
+    """Counters that carry from the nonce's low 64 bits into its high half
+    (and wrap at 2^128) inside the LL band, which several forward wavefronts
+    encrypt: the same fragments as the oracle, and an exact restore."""
+    n, width, levels = 2000 * 50, 2000, 3   # LL 7 x 250: 219 keystream blocks
+    rng = np.random.default_rng(91)
+    buf = rng.integers(0, 256, n, dtype=np.uint8)
+    key, nonce = rng.bytes(16), bytes.fromhex(nonce_hex)
+    _say(f"case nonce={nonce_hex}")
+    priv, pub = _gpu_protect(buf, width, levels, key, nonce)
+    opriv, opub = fragment.protect(buf, width, levels, key, nonce)
+    assert priv == bytes(opriv) and pub == bytes(opub)
+    assert _gpu_restore(priv, pub, n, width, levels, key, nonce) == buf.tobytes()
+
+
 @pytest.mark.parametrize("n,width,levels", [c for c in CASES if c[0] <= 300000])
 def test_restore_of_arbitrary_fragments_matches_oracle(n, width, levels):
     """The inverse on its own: random (not protect-produced) fragments."""
