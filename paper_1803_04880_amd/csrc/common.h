@@ -96,25 +96,39 @@ __device__ __forceinline__ void counter_block(const uint32_t *kw, uint64_t j, ui
 
 // One AES-128 encryption; `te` points at four 256-word tables in LDS
 // (te[256 r + x] = rotl(te0[x], 8 r)), `rk` at the 44 round-key words.
+// Each column of a middle round is four table words and a round-key word
+// XORed together: two 3-input bit operations (truth table 0x96 = a ^ b ^ c).
+// The last round takes the S-box byte (byte 1 of te0[x]) of four lookups
+// with two byte permutes and joins them with the round key in one 3-input
+// operation (truth table 0x56 = (a | b) ^ c).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ void aes_encrypt(const uint32_t *te, const uint32_t *rk, uint32_t w[4]) {
   uint32_t s0 = w[0] ^ rk[0], s1 = w[1] ^ rk[1], s2 = w[2] ^ rk[2], s3 = w[3] ^ rk[3];
 #define DWTFRAG_TE(r, v) te[256 * (r) + (((v) >> (8 * (r))) & 0xFF)]
 #pragma unroll
   for (int rnd = 1; rnd < 10; ++rnd) {
-    uint32_t t0 = DWTFRAG_TE(0, s0) ^ DWTFRAG_TE(1, s1) ^ DWTFRAG_TE(2, s2) ^ DWTFRAG_TE(3, s3) ^ rk[4 * rnd + 0];
-    uint32_t t1 = DWTFRAG_TE(0, s1) ^ DWTFRAG_TE(1, s2) ^ DWTFRAG_TE(2, s3) ^ DWTFRAG_TE(3, s0) ^ rk[4 * rnd + 1];
-    uint32_t t2 = DWTFRAG_TE(0, s2) ^ DWTFRAG_TE(1, s3) ^ DWTFRAG_TE(2, s0) ^ DWTFRAG_TE(3, s1) ^ rk[4 * rnd + 2];
-    uint32_t t3 = DWTFRAG_TE(0, s3) ^ DWTFRAG_TE(1, s0) ^ DWTFRAG_TE(2, s1) ^ DWTFRAG_TE(3, s2) ^ rk[4 * rnd + 3];
+    const uint32_t t0 = xor3(xor3(DWTFRAG_TE(0, s0), DWTFRAG_TE(1, s1), DWTFRAG_TE(2, s2)), DWTFRAG_TE(3, s3), rk[4 * rnd + 0]);
+    const uint32_t t1 = xor3(xor3(DWTFRAG_TE(0, s1), DWTFRAG_TE(1, s2), DWTFRAG_TE(2, s3)), DWTFRAG_TE(3, s0), rk[4 * rnd + 1]);
+    const uint32_t t2 = xor3(xor3(DWTFRAG_TE(0, s2), DWTFRAG_TE(1, s3), DWTFRAG_TE(2, s0)), DWTFRAG_TE(3, s1), rk[4 * rnd + 2]);
+    const uint32_t t3 = xor3(xor3(DWTFRAG_TE(0, s3), DWTFRAG_TE(1, s0), DWTFRAG_TE(2, s1)), DWTFRAG_TE(3, s2), rk[4 * rnd + 3]);
     s0 = t0; s1 = t1; s2 = t2; s3 = t3;
   }
 #undef DWTFRAG_TE
-  // last round: SubBytes + ShiftRows only; S[x] is byte 1 of te0[x]
-#define DWTFRAG_S(v, r) ((te[((v) >> (8 * (r))) & 0xFF] >> 8) & 0xFF)
-  w[0] = (DWTFRAG_S(s0, 0) | (DWTFRAG_S(s1, 1) << 8) | (DWTFRAG_S(s2, 2) << 16) | (DWTFRAG_S(s3, 3) << 24)) ^ rk[40];
-  w[1] = (DWTFRAG_S(s1, 0) | (DWTFRAG_S(s2, 1) << 8) | (DWTFRAG_S(s3, 2) << 16) | (DWTFRAG_S(s0, 3) << 24)) ^ rk[41];
-  w[2] = (DWTFRAG_S(s2, 0) | (DWTFRAG_S(s3, 1) << 8) | (DWTFRAG_S(s0, 2) << 16) | (DWTFRAG_S(s1, 3) << 24)) ^ rk[42];
-  w[3] = (DWTFRAG_S(s3, 0) | (DWTFRAG_S(s0, 1) << 8) | (DWTFRAG_S(s1, 2) << 16) | (DWTFRAG_S(s2, 3) << 24)) ^ rk[43];
-#undef DWTFRAG_S
+  // last round: SubBytes + ShiftRows + the last round key
+#define DWTFRAG_L(v, r) te[((v) >> (8 * (r))) & 0xFF]
+#define DWTFRAG_LAST(a, b, c, d, k)                                                             \
+  __builtin_amdgcn_bitop3_b32(__builtin_amdgcn_perm(DWTFRAG_L(b, 1), DWTFRAG_L(a, 0), 0x0c0c0501u), \
+                              __builtin_amdgcn_perm(DWTFRAG_L(d, 3), DWTFRAG_L(c, 2), 0x05010c0cu), \
+                              (k), 0x56)
+  w[0] = DWTFRAG_LAST(s0, s1, s2, s3, rk[40]);
+  w[1] = DWTFRAG_LAST(s1, s2, s3, s0, rk[41]);
+  w[2] = DWTFRAG_LAST(s2, s3, s0, s1, rk[42]);
+  w[3] = DWTFRAG_LAST(s3, s0, s1, s2, rk[43]);
+#undef DWTFRAG_LAST
+#undef DWTFRAG_L
 }
 
 static __constant__ AesTables c_aes = make_aes_tables();
