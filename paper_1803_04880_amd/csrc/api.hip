@@ -133,9 +133,29 @@ int64_t device_slots(bool forward, int L, int C1, bool bytes) {
   return slots;
 }
 
-// Fill stage s's parameters.  forward selects the halo shape of the direction.
+// SIMDs of the current device (4 per compute unit), cached per device.
+int64_t device_simds() {
+  constexpr int kDev = 16;
+  static std::atomic<int> cache[kDev];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDev) dev = -1;
+  if (dev >= 0) {
+    const int v = cache[dev].load(std::memory_order_relaxed);
+    if (v > 0) return v;
+  }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev < 0 ? 0 : dev) != hipSuccess)
+    cus = 0;
+  const int simds = cus > 0 ? 4 * cus : 1024;
+  if (dev >= 0) cache[dev].store(simds, std::memory_order_relaxed);
+  return simds;
+}
+
+// Fill stage s's parameters.  forward selects the halo shape of the direction;
+// alone: the stage runs as its own launch (not as one item of a batch that
+// shares the device).
 int plan_stage(const Geometry &g, int s, bool forward, const dwtfrag_launch *launch,
-               const AesKey &key, StageParams *P, int *L_out, int *C1_out) {
+               const AesKey &key, StageParams *P, int *L_out, int *C1_out, bool alone) {
   std::memset(P, 0, sizeof(*P));
   const int lv0 = kMaxFused * s;  // global level of the stage input
   const int L = int(std::min<uint32_t>(kMaxFused, g.levels - lv0));
@@ -177,10 +197,14 @@ int plan_stage(const Geometry &g, int s, bool forward, const dwtfrag_launch *lau
     n_seg = (P->H + own_h - 1) / own_h;
   } else {
     // one round of resident wavefronts: as many segments as fill the device
-    // once, each at least two units long (halo work stays below the owned)
+    // once, each at least two units long (halo work stays below the owned).
+    // A launch of its own whose grid stays within one wavefront per SIMD
+    // even at one unit per segment takes one unit per segment: the extra
+    // halo rows run on otherwise idle SIMDs and each stream is shorter.
     const int64_t slots = device_slots(forward, L, C1, s == 0);
     n_seg = std::max<int64_t>(1, slots / P->n_win);
-    n_seg = std::min<int64_t>(n_seg, std::max(1, P->units / 2));
+    const int min_units = (alone && int64_t(P->units) * P->n_win <= device_simds()) ? 1 : 2;
+    n_seg = std::min<int64_t>(n_seg, std::max(1, P->units / min_units));
   }
   P->n_seg = int32_t(std::min<int64_t>(std::max<int64_t>(n_seg, 1), P->units));
   const int64_t waves = int64_t(P->n_win) * P->n_seg;
@@ -214,7 +238,7 @@ int plan_single_stage(uint64_t n, uint32_t width, uint32_t levels, bool forward,
   const int rc = make_geometry(n, width, levels, &g);
   if (rc != DWTFRAG_OK) return rc;
   *priv_bytes = g.priv_bytes;
-  return plan_stage(g, 0, forward, launch, key, P, L, C1);
+  return plan_stage(g, 0, forward, launch, key, P, L, C1, false);
 }
 }  // namespace dwtfrag
 
@@ -265,7 +289,7 @@ int dwtfrag_protect(const uint8_t *in, uint64_t n, uint32_t width, uint32_t leve
   std::vector<StageParams> plans(g.stages);
   std::vector<int> Ls(g.stages), C1s(g.stages);
   for (int s = 0; s < g.stages; ++s) {
-    rc = plan_stage(g, s, true, launch, k, &plans[s], &Ls[s], &C1s[s]);
+    rc = plan_stage(g, s, true, launch, k, &plans[s], &Ls[s], &C1s[s], true);
     if (rc != DWTFRAG_OK) return rc;
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -298,7 +322,7 @@ int dwtfrag_restore(const uint8_t *priv, const int16_t *pub, uint64_t n, uint32_
   std::vector<StageParams> plans(g.stages);
   std::vector<int> Ls(g.stages), C1s(g.stages);
   for (int s = 0; s < g.stages; ++s) {
-    rc = plan_stage(g, s, false, launch, k, &plans[s], &Ls[s], &C1s[s]);
+    rc = plan_stage(g, s, false, launch, k, &plans[s], &Ls[s], &C1s[s], true);
     if (rc != DWTFRAG_OK) return rc;
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
