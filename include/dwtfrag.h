@@ -190,8 +190,11 @@ void dwtfrag_batch_destroy(dwtfrag_batch *plan);
  * `trials` times each, with HIP events on `stream`, and return the fastest in
  * *best (and its time in microseconds in *best_us).  `scratch` (device) holds
  * the fragments, the output and the workspace: at least
- * geom.priv_bytes + geom.pub_bytes + n + geom.workspace_bytes + 768 bytes.
- * Synchronises `stream`. */
+ * geom.priv_bytes + geom.pub_bytes + n + geom.workspace_bytes + 768 bytes,
+ * 256-byte aligned.  Synchronises `stream`.  Errors: EINVAL for a null
+ * pointer or trials == 0, EWORKSPACE for a short or misaligned scratch,
+ * the geometry's own errors, else the first failing protect / restore
+ * call's code, or EDEVICE for a failing event call. */
 int dwtfrag_autotune(const uint8_t *in, uint64_t n, uint32_t width, uint32_t levels,
                      void *scratch, uint64_t scratch_bytes, uint32_t trials,
                      dwtfrag_launch *best, float *best_us, void *stream);

@@ -371,7 +371,7 @@ int dwtfrag_autotune(const uint8_t *in, uint64_t n, uint32_t width, uint32_t lev
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return DWTFRAG_EDEVICE;
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return DWTFRAG_EDEVICE;
   }
   float best_t = -1.0f;
@@ -383,20 +383,25 @@ int dwtfrag_autotune(const uint8_t *in, uint64_t n, uint32_t width, uint32_t lev
     if (levels % kMaxFused == 0 && c == 8) continue;  // a four-level stage needs 16 columns
     for (uint32_t r : rows) {
       const dwtfrag_launch ln{r, c};
-      // one untimed pair, then `trials` timed pairs
-      if (dwtfrag_protect(in, n, width, levels, key, nonce, priv, pub, ws, g.ws_bytes, &ln, st) ||
-          dwtfrag_restore(priv, pub, n, width, levels, key, nonce, out, ws, g.ws_bytes, &ln, st)) {
+      // one untimed pair, then `trials` timed pairs; the first failing call's
+      // code is returned
+      auto pair = [&]() {
+        const int r = dwtfrag_protect(in, n, width, levels, key, nonce, priv, pub, ws, g.ws_bytes, &ln, st);
+        return r != DWTFRAG_OK ? r
+                               : dwtfrag_restore(priv, pub, n, width, levels, key, nonce, out, ws,
+                                                 g.ws_bytes, &ln, st);
+      };
+      rc = pair();
+      if (rc != DWTFRAG_OK) break;
+      if (hipEventRecord(e0, st) != hipSuccess) {
         rc = DWTFRAG_EDEVICE;
         break;
       }
-      hipEventRecord(e0, st);
-      for (uint32_t t = 0; t < trials; ++t) {
-        dwtfrag_protect(in, n, width, levels, key, nonce, priv, pub, ws, g.ws_bytes, &ln, st);
-        dwtfrag_restore(priv, pub, n, width, levels, key, nonce, out, ws, g.ws_bytes, &ln, st);
-      }
-      hipEventRecord(e1, st);
+      for (uint32_t t = 0; t < trials && rc == DWTFRAG_OK; ++t) rc = pair();
+      if (rc != DWTFRAG_OK) break;
       float ms = 0.0f;
-      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
         rc = DWTFRAG_EDEVICE;
         break;
       }
@@ -408,8 +413,8 @@ int dwtfrag_autotune(const uint8_t *in, uint64_t n, uint32_t width, uint32_t lev
     }
     if (rc != DWTFRAG_OK) break;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rc != DWTFRAG_OK) return rc;
   *best = best_l;
   if (best_us) *best_us = best_t;
