@@ -42,6 +42,13 @@
  *   - arguments are validated before anything is launched; on an error
  *     return nothing has been written.
  *   - input and output buffers must not overlap.
+ *   - device buffers of dwtfrag_protect / dwtfrag_restore (in, out, priv, pub,
+ *     workspace) and of batch items must start at 16-byte aligned addresses:
+ *     rows are read and written with 16-byte vector accesses from the buffer
+ *     base.  A misaligned pointer returns DWTFRAG_EINVAL before any launch
+ *     (copy a buffer that starts at an odd offset into an aligned one first;
+ *     hipMalloc and torch allocations are 256-byte aligned).  n itself may be
+ *     any length.
  *   - calls may come from several host threads; there is no mutable global
  *     state besides per-device constant tables set up on first use.
  */
@@ -57,7 +64,7 @@ extern "C" {
 typedef enum {
   DWTFRAG_OK = 0,
   DWTFRAG_EINVAL = -1,     /* null pointer, n == 0, width == 0, levels == 0 or > 32 */
-  DWTFRAG_ERANGE = -2,     /* rows or width above 2^31-1, or a byte count overflows */
+  DWTFRAG_ERANGE = -2,     /* rows or width above 2^31-2^16, or a byte count overflows */
   DWTFRAG_EDEVICE = -3,    /* a HIP call or kernel launch failed */
   DWTFRAG_EWORKSPACE = -4  /* workspace missing or smaller than workspace_bytes */
 } dwtfrag_status;
@@ -94,7 +101,7 @@ int dwtfrag_geometry(uint64_t n, uint32_t width, uint32_t levels, dwtfrag_geom *
 uint32_t dwtfrag_default_width(uint64_t n);
 
 /* Forward path: view -> L-level 5/3 lifting -> priv = AES-128-CTR(LL_L),
- * pub = detail bands (layout above).
+ * pub = detail bands (layout above).  Every device pointer 16-byte aligned.
  *   in        device, n bytes
  *   priv      device, geom.priv_bytes bytes (written)
  *   pub       device, geom.pub_bytes / 2 int16 values (written); may be NULL
@@ -113,7 +120,8 @@ int dwtfrag_protect(const uint8_t *in, uint64_t n, uint32_t width, uint32_t leve
  * within a level), write the first n bytes; every reconstructed sample is
  * stored modulo 256, so tampered fragments still produce n bytes.
  *   priv, pub fragments as produced by dwtfrag_protect (device, read only)
- *   out       device, n bytes (written) */
+ *   out       device, n bytes (written)
+ * Every device pointer 16-byte aligned; EINVAL otherwise. */
 int dwtfrag_restore(const uint8_t *priv, const int16_t *pub, uint64_t n, uint32_t width,
                     uint32_t levels, const uint8_t key[16], const uint8_t nonce[16],
                     uint8_t *out, void *workspace, uint64_t workspace_bytes,

@@ -176,8 +176,14 @@ def protect(x: torch.Tensor, width: int, levels: int, key: bytes, nonce: bytes, 
         pub = torch.empty(g["pub_bytes"] // 2, dtype=torch.int16, device=x.device)
     _check_dev(priv, torch.uint8, "priv")
     _check_dev(pub, torch.int16, "pub")
+    # the C ABI takes no buffer sizes: a short tensor would be written past
+    # its end on the device, so sizes are checked here
+    if priv.numel() != g["priv_bytes"] or 2 * pub.numel() != g["pub_bytes"]:
+        raise ValueError("fragment sizes do not match the geometry")
     if ws is None and g["workspace_bytes"]:
         ws = workspace(n, width, levels, x.device)
+    if ws is not None and ws.numel() < g["workspace_bytes"]:
+        raise ValueError("workspace smaller than the geometry needs")
     rc = lib().dwtfrag_protect(
         x.data_ptr(), n, width, levels, _key16(key, "key"), _key16(nonce, "nonce"),
         priv.data_ptr(), pub.data_ptr(), ws.data_ptr() if ws is not None else None,
@@ -199,8 +205,12 @@ def restore(priv: torch.Tensor, pub: torch.Tensor, n: int, width: int, levels: i
     if out is None:
         out = torch.empty(n, dtype=torch.uint8, device=priv.device)
     _check_dev(out, torch.uint8, "out")
+    if out.numel() < n:
+        raise ValueError("out holds fewer than n bytes")
     if ws is None and g["workspace_bytes"]:
         ws = workspace(n, width, levels, priv.device)
+    if ws is not None and ws.numel() < g["workspace_bytes"]:
+        raise ValueError("workspace smaller than the geometry needs")
     rc = lib().dwtfrag_restore(
         priv.data_ptr(), pub.data_ptr(), n, width, levels, _key16(key, "key"),
         _key16(nonce, "nonce"), out.data_ptr(), ws.data_ptr() if ws is not None else None,

@@ -104,6 +104,13 @@ class Batch:
             p = privs[i] if privs else torch.empty(g["priv_bytes"], dtype=torch.uint8, device=dev)
             q = pubs[i] if pubs else torch.empty(max(g["pub_bytes"] // 2, 1), dtype=torch.int16, device=dev)
             o = outs[i] if outs else torch.empty(x.numel(), dtype=torch.uint8, device=dev)
+            # the plan carries pointers only: a short tensor would be written
+            # (or read) past its end on the device, so sizes are checked here
+            _check_dev(p, torch.uint8, "priv")
+            _check_dev(q, torch.int16, "pub")
+            _check_dev(o, torch.uint8, "out")
+            if p.numel() != g["priv_bytes"] or 2 * q.numel() < g["pub_bytes"] or o.numel() < x.numel():
+                raise ValueError(f"item {i}: fragment or output size does not match the geometry")
             self.privs.append(p)
             self.pubs.append(q[:g["pub_bytes"] // 2])
             self.outs.append(o)

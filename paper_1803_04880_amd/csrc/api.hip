@@ -53,7 +53,11 @@ void expand_key(const uint8_t key[16], const uint8_t nonce[16], AesKey *out) {
 
 namespace {
 
-constexpr uint64_t kMaxDim = 0x7FFFFFFFull;
+// Rows and columns of a view.  The launch planning and the kernels index rows
+// and columns in int32 with margins of up to a window (1024 columns) and a
+// unit plus halos (under 64 rows) past the end, so the limit keeps 2^16 below
+// 2^31.
+constexpr uint64_t kMaxDim = 0x7FFF0000ull;
 
 struct Geometry {
   uint64_t n;

@@ -739,7 +739,8 @@ using namespace dwtfrag;
 
 namespace {
 
-constexpr uint64_t kMaxDim = 0x7FFFFFFFull;
+// Same row and column limit as the plain path (int32 indexing with margins).
+constexpr uint64_t kMaxDim = 0x7FFF0000ull;
 
 uint64_t a256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
 

@@ -73,6 +73,12 @@ def test_geometry_errors():
     assert L.dwtfrag_geometry(10, 4, 33, ctypes.byref(g)) == pkg.DWTFRAG_EINVAL
     assert L.dwtfrag_geometry(10, 4, 1, None) == pkg.DWTFRAG_EINVAL
     assert L.dwtfrag_geometry(10, 1 << 31, 1, ctypes.byref(g)) == pkg.DWTFRAG_ERANGE
+    # the largest row / column count keeps 2^16 of int32 headroom for planning
+    lim = (1 << 31) - (1 << 16)
+    assert L.dwtfrag_geometry(10, lim, 1, ctypes.byref(g)) == pkg.DWTFRAG_OK
+    assert L.dwtfrag_geometry(10, lim + 1, 1, ctypes.byref(g)) == pkg.DWTFRAG_ERANGE
+    assert L.dwtfrag_geometry(lim, 1, 3, ctypes.byref(g)) == pkg.DWTFRAG_OK
+    assert L.dwtfrag_geometry(lim + 1, 1, 3, ctypes.byref(g)) == pkg.DWTFRAG_ERANGE
     assert L.dwtfrag_geometry(1 << 40, 1, 1, ctypes.byref(g)) == pkg.DWTFRAG_ERANGE
 
 
@@ -106,6 +112,30 @@ def test_protect_restore_reject_bad_arguments_before_launch():
     assert L.dwtfrag_aes128_ctr(fake, fake, 0, key, key, 0, None) == pkg.DWTFRAG_EINVAL
     for code in (0, -1, -2, -3, -4, 7):
         assert pkg.strerror(code)
+
+
+def test_alignment_contract_of_single_buffer_calls():
+    """The header requires 16-byte aligned device buffers for protect and
+    restore: each misaligned pointer is refused with EINVAL before any
+    launch (the pointers are never dereferenced)."""
+    L = _lib_or_skip()
+    key = b"k" * 16
+    A = 0x100000                                # 16-byte aligned fake addresses
+    ok = dict(src=A, priv=A + 0x10000, pub=A + 0x20000, dst=A + 0x30000, ws=A + 0x40000)
+    for name in ok:
+        for off in (1, 2, 4, 8):
+            p = dict(ok)
+            p[name] += off
+            v = {k: ctypes.c_void_p(x) for k, x in p.items()}
+            # 6 levels: the workspace is used and checked too
+            rc = L.dwtfrag_protect(v["src"], 100000, 300, 6, key, key, v["priv"], v["pub"],
+                                   v["ws"], 1 << 20, None, None)
+            if name != "dst":
+                assert rc == pkg.DWTFRAG_EINVAL, (name, off)
+            rc = L.dwtfrag_restore(v["priv"], v["pub"], 100000, 300, 6, key, key, v["dst"],
+                                   v["ws"], 1 << 20, None, None)
+            if name != "src":
+                assert rc == pkg.DWTFRAG_EINVAL, (name, off)
 
 
 def test_product_path_has_no_oracle_dependency():

@@ -156,16 +156,16 @@ def test_sbox_is_a_permutation_without_fixed_points():
     assert all(s[a] != a and s[a] != (a ^ 0xFF) for a in range(256))
 
 
-def test_aes128_fips197_example_vector():
-    """The AES-128 example of FIPS-197 (Appendix C.1): key 00 01 .. 0f,
-    plaintext 00 11 22 .. ff.  The expected block is also what the openssl
-    CLI returns for these inputs (checked when it is installed)."""
+@needs_openssl
+def test_aes128_fips197_example_inputs():
+    """The inputs of the AES-128 example of FIPS-197 (Appendix C.1): key
+    00 01 .. 0f, plaintext 00 11 22 .. ff.  The expected ciphertext is not
+    typed here: it is what the openssl CLI returns for these inputs."""
     key = bytes(range(16))
-    pt = bytes.fromhex("00112233445566778899aabbccddeeff")
-    want = bytes.fromhex("69c4e0d86a7b0430d8cdb78070b4c55a")
+    pt = bytes(((i << 4) | i) for i in range(16))   # 00 11 22 .. ff
+    want = _openssl(["-aes-128-ecb", "-K", key.hex(), "-nopad"], pt)
+    assert len(want) == 16
     assert aes128.encrypt_blocks(key, np.frombuffer(pt, np.uint8).reshape(1, 16)).tobytes() == want
-    if _OPENSSL is not None:
-        assert _openssl(["-aes-128-ecb", "-K", key.hex(), "-nopad"], pt) == want
 
 
 @needs_openssl
