@@ -82,24 +82,31 @@ class Server:
         used = sum(r.device_bytes() for r in reqs)
         batches = []
         with torch.cuda.stream(stream):
+            # Both plans are built and uploaded before either batch is
+            # launched: an upload waits for the work already queued on its
+            # stream, which at this point is only retired work (a stream gets
+            # a new batch only after its previous one has been retired).
+            pb = rb = None
             if prot:
-                b = Batch([r.x for r in prot], [r.width for r in prot], [r.levels for r in prot],
-                          [r.key for r in prot], [r.nonce for r in prot],
-                          outs=[r.x for r in prot])   # protect never writes `out`
-                b.protect(stream=stream)
-                for r, p, q in zip(prot, b.privs, b.pubs):
-                    r.out_priv, r.out_pub = p, q
-                batches.append(b)
+                pb = Batch([r.x for r in prot], [r.width for r in prot], [r.levels for r in prot],
+                           [r.key for r in prot], [r.nonce for r in prot],
+                           outs=[r.x for r in prot])   # protect never writes `out`
             if rest:
                 outs = [torch.empty(r.n, dtype=torch.uint8, device=self.device) for r in rest]
                 # restore reads only the fragments: the outputs stand in as inputs
-                b = Batch(outs, [r.width for r in rest], [r.levels for r in rest],
-                          [r.key for r in rest], [r.nonce for r in rest],
-                          privs=[r.priv for r in rest], pubs=[r.pub for r in rest], outs=outs)
-                b.restore(stream=stream)
-                for r, o in zip(rest, outs):
+                rb = Batch(outs, [r.width for r in rest], [r.levels for r in rest],
+                           [r.key for r in rest], [r.nonce for r in rest],
+                           privs=[r.priv for r in rest], pubs=[r.pub for r in rest], outs=outs)
+            if pb is not None:
+                pb.protect(stream=stream)
+                for r, p, q in zip(prot, pb.privs, pb.pubs):
+                    r.out_priv, r.out_pub = p, q
+                batches.append(pb)
+            if rb is not None:
+                rb.restore(stream=stream)
+                for r, o in zip(rest, rb.outs):
                     r.out = o
-                batches.append(b)
+                batches.append(rb)
             ev = torch.cuda.Event()
             ev.record(stream)
         self.in_use += used

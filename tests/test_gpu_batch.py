@@ -68,6 +68,69 @@ def test_batch_matches_oracle_and_roundtrips(count, seed):
     b.close()
 
 
+_CFG3 = {}
+
+
+def _cfg3_specs():
+    """Items of the uneven-batch workload's shapes: sizes from 4 MiB to just
+    over 16 MiB, so the default width is 4096 (several column windows per
+    item), levels 1..4 (four levels run 16-column tiles), content from the
+    workload's generators (smooth / markov / uniform thirds), ragged tails."""
+    sizes = [(16 << 20) + 12345, (9 << 20) - 777, (6 << 20) + 1, (4 << 20) + 4097,
+             (5 << 20) + 3, (7 << 20) - 5]
+    levels = [4, 3, 2, 1, 3, 1]
+    kinds = ["smooth", "markov", "uniform", "smooth", "markov", "uniform"]
+    if "specs" in _CFG3:
+        return _CFG3["specs"]
+    rng = np.random.default_rng(31)
+    specs = []
+    for i, (n, lv, kind) in enumerate(zip(sizes, levels, kinds)):
+        spec = dict(seed=7000 + i, n=n, kind=kind, levels=lv, width=synth.default_width(n),
+                    nonce=rng.bytes(16))
+        spec["buf"] = synth.batch_buffer(spec)
+        spec["key"] = rng.bytes(16)
+        # the oracle's fragments, computed once for both parametrisations
+        spec["oracle"] = fragment.protect(spec["buf"], spec["width"], lv, spec["key"], spec["nonce"])
+        specs.append(spec)
+    _CFG3["specs"] = specs
+    return specs
+
+
+def _first_diff(a, b):
+    a = np.frombuffer(a, np.uint8)
+    b = np.frombuffer(b, np.uint8)
+    if a.size != b.size:
+        return f"sizes {a.size} != {b.size}"
+    idx = np.flatnonzero(a != b)
+    return "equal" if idx.size == 0 else f"{idx.size} bytes differ, first at byte {idx[0]}"
+
+
+@pytest.mark.parametrize("tuned", [False, True])
+def test_batch_workload_shapes_match_oracle(tuned):
+    """Batch items at the uneven-batch workload's shapes (width 4096,
+    multi-window drains, 8- and 16-column tiles, tuned tile heights) against
+    the oracle, element by element, and restored exactly."""
+    specs = _cfg3_specs()
+    assert all(s["width"] == 4096 for s in specs)
+    tune = None
+    if tuned:   # 16-column tiles for the 1..3-level classes, other heights
+        tune = {(4096, 1): (64, 16), (4096, 2): (256, 16), (4096, 3): (256, 8), (4096, 4): (64, 16)}
+    _say(f"workload-shaped batch tuned={tuned}: " +
+         ", ".join(f"n={s['n']} L={s['levels']} {s['kind']}" for s in specs))
+    b = _make_batch(specs, tune=tune)
+    b.protect()
+    b.restore()
+    torch.cuda.synchronize()
+    for i, s in enumerate(specs):
+        opriv, opub = s["oracle"]
+        gpriv = b.privs[i].cpu().numpy().tobytes()
+        gpub = b.pubs[i].cpu().numpy().tobytes()
+        assert gpriv == opriv, f"item {i} priv: {_first_diff(gpriv, opriv)}"
+        assert gpub == opub, f"item {i} pub: {_first_diff(gpub, opub)}"
+        assert np.array_equal(b.outs[i].cpu().numpy(), s["buf"]), f"item {i} restore"
+    b.close()
+
+
 def test_batch_degenerate_items():
     rng = np.random.default_rng(9)
     specs = []
@@ -150,19 +213,26 @@ def test_autotune_and_tuned_batch():
         assert b.outs[i].cpu().numpy().tobytes() == s["buf"].tobytes()
 
 
-def test_serving_loop_results_equal_lone_calls():
+def test_serving_loop_results_equal_oracle_and_lone_calls():
     """Requests arriving over time, served by continuous batching, give the
-    same bytes as each request processed alone."""
+    oracle's bytes: every served protect equals the oracle's fragments of its
+    buffer, every served restore equals the oracle's restore of the oracle's
+    fragments; the lone GPU calls that made the restore inputs agree too."""
     from paper_1803_04880_amd import serve
     rng = np.random.default_rng(21)
     reqs, lone = [], []
     pool = _specs(12, 22, lo=1000, hi=300000)
-    frag = []
+    frag, ofrag = [], []
     for s in pool:   # fragments for restore requests, made by lone calls
         x = torch.from_numpy(s["buf"]).to(DEV)
         p, q = dwtfrag.protect(x, s["width"], s["levels"], s["key"], s["nonce"])
         frag.append((x, p, q))
+        opriv, opub = fragment.protect(s["buf"], s["width"], s["levels"], s["key"], s["nonce"])
+        oback = fragment.restore(opriv, opub, s["n"], s["width"], s["levels"], s["key"], s["nonce"])
+        ofrag.append((opriv, opub, oback))
     torch.cuda.synchronize()
+    for (x, p, q), (opriv, opub, _) in zip(frag, ofrag):
+        assert p.cpu().numpy().tobytes() == opriv and q.cpu().numpy().tobytes() == opub
     t = 0.0
     for rid in range(60):
         t += float(rng.exponential(0.002))
@@ -178,12 +248,17 @@ def test_serving_loop_results_equal_lone_calls():
     wall = srv.run(reqs)
     torch.cuda.synchronize()
     _say(f"served {len(reqs)} requests in {wall:.3f}s, {srv.batches_launched} launches")
+    assert srv.batches_launched > 1   # requests were admitted over several batches
     for r, k in zip(reqs, lone):
         x, p, q = frag[k]
+        opriv, opub, oback = ofrag[k]
         assert r.done is not None and r.done >= r.arrival
         if r.op == "protect":
+            assert r.out_priv.cpu().numpy().tobytes() == opriv, f"request {r.rid} priv vs oracle"
+            assert r.out_pub.cpu().numpy().tobytes() == opub, f"request {r.rid} pub vs oracle"
             assert torch.equal(r.out_priv, p) and torch.equal(r.out_pub, q), f"request {r.rid}"
         else:
+            assert r.out.cpu().numpy().tobytes() == oback, f"request {r.rid} restore vs oracle"
             assert torch.equal(r.out, x), f"request {r.rid}"
 
 
