@@ -19,4 +19,8 @@ Modules
             pin dwt53 in tests.
   learned   learned context-MLP predictor variant of the lifting predict step
             (integer forward, fp64 training gradients).
+  sha2      SHA-256 / SHA-512 (FIPS 180-4, constants derived from prime roots).
+  se8       the thesis's per-8x8-block protection (Ch. 5 section 5.2.1):
+            2-level block lifting, SHA keystreams XORed over the public
+            fragments, 10/11-bit packed records, AES-CTR private fragment.
 """
