@@ -66,7 +66,8 @@ typedef enum {
   DWTFRAG_EINVAL = -1,     /* null pointer, n == 0, width == 0, levels == 0 or > 32 */
   DWTFRAG_ERANGE = -2,     /* rows or width above 2^31-2^16, or a byte count overflows */
   DWTFRAG_EDEVICE = -3,    /* a HIP call or kernel launch failed */
-  DWTFRAG_EWORKSPACE = -4  /* workspace missing or smaller than workspace_bytes */
+  DWTFRAG_EWORKSPACE = -4, /* workspace missing or smaller than workspace_bytes */
+  DWTFRAG_ESCRATCH = -5    /* dwtfrag_protect_noalloc: workspace_bytes above its 16 MiB */
 } dwtfrag_status;
 
 /* Geometry of one buffer; filled by dwtfrag_geometry. */
@@ -114,6 +115,23 @@ int dwtfrag_protect(const uint8_t *in, uint64_t n, uint32_t width, uint32_t leve
                     uint8_t *priv, int16_t *pub,
                     void *workspace, uint64_t workspace_bytes,
                     const dwtfrag_launch *launch, void *stream);
+
+/* dwtfrag_protect for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same fragments, with the workspace of levels > 4 taken from a static
+ * 16 MiB device array inside the library instead of a caller buffer.  The
+ * call allocates nothing.  Each GPU the library runs on holds its own copy
+ * of the array until the process ends; its device address is looked up on
+ * the first call on that device.  Every call on one device shares the array,
+ * so calls that may overlap on one device (several streams, several host
+ * threads) race and must be ordered by the caller; calls with levels <= 4 do
+ * not touch it.  Arguments as dwtfrag_protect; DWTFRAG_ESCRATCH (before any
+ * launch) when geom.workspace_bytes exceeds 16 MiB (about n > 2 GiB at
+ * levels > 4); DWTFRAG_EDEVICE if the array's address cannot be found. */
+int dwtfrag_protect_noalloc(const uint8_t *in, uint64_t n, uint32_t width, uint32_t levels,
+                            const uint8_t key[16], const uint8_t nonce[16],
+                            uint8_t *priv, int16_t *pub,
+                            const dwtfrag_launch *launch, void *stream);
 
 /* Inverse path (Ch. 5 section 5.2.3, exact inverse): decrypt priv with the
  * same keystream, inverse lifting levels L..1 (vertical then horizontal

@@ -24,6 +24,7 @@ DWTFRAG_EINVAL = -1
 DWTFRAG_ERANGE = -2
 DWTFRAG_EDEVICE = -3
 DWTFRAG_EWORKSPACE = -4
+DWTFRAG_ESCRATCH = -5
 
 
 class DwtfragError(RuntimeError):
@@ -46,7 +47,8 @@ class Launch(ctypes.Structure):
 
 _lib = None
 
-EXPORTS = ("dwtfrag_geometry", "dwtfrag_default_width", "dwtfrag_protect", "dwtfrag_restore",
+EXPORTS = ("dwtfrag_geometry", "dwtfrag_default_width", "dwtfrag_protect",
+           "dwtfrag_protect_noalloc", "dwtfrag_restore",
            "dwtfrag_aes128_ctr", "dwtfrag_strerror",
            "dwtfrag_learned_geometry", "dwtfrag_protect_learned", "dwtfrag_restore_learned",
            "dwtfrag_learned_pairs", "dwtfrag_trainer_workspace_bytes", "dwtfrag_trainer_init",
@@ -75,6 +77,10 @@ def lib():
                                   ctypes.c_char_p, ctypes.c_char_p, u8p, i16p, vp,
                                   ctypes.c_uint64, ctypes.POINTER(Launch), vp]
     L.dwtfrag_protect.restype = ctypes.c_int
+    L.dwtfrag_protect_noalloc.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                          ctypes.c_char_p, ctypes.c_char_p, u8p, i16p,
+                                          ctypes.POINTER(Launch), vp]
+    L.dwtfrag_protect_noalloc.restype = ctypes.c_int
     L.dwtfrag_restore.argtypes = [u8p, i16p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                   ctypes.c_char_p, ctypes.c_char_p, u8p, vp, ctypes.c_uint64,
                                   ctypes.POINTER(Launch), vp]
@@ -193,6 +199,25 @@ def protect(x: torch.Tensor, width: int, levels: int, key: bytes, nonce: bytes, 
     return priv, pub
 
 
+def protect_noalloc(x: torch.Tensor, width: int, levels: int, key: bytes, nonce: bytes, *,
+                    priv: torch.Tensor, pub: torch.Tensor, launch=None, stream=None):
+    """``protect`` into caller-given fragment tensors through the entry point
+    that allocates nothing (its workspace is the library's static array)."""
+    _check_dev(x, torch.uint8, "x")
+    _check_dev(priv, torch.uint8, "priv")
+    _check_dev(pub, torch.int16, "pub")
+    n = x.numel()
+    g = geometry(n, width, levels)
+    if priv.numel() != g["priv_bytes"] or 2 * pub.numel() != g["pub_bytes"]:
+        raise ValueError("fragment sizes do not match the geometry")
+    rc = lib().dwtfrag_protect_noalloc(
+        x.data_ptr(), n, width, levels, _key16(key, "key"), _key16(nonce, "nonce"),
+        priv.data_ptr(), pub.data_ptr(), _launch(launch), _stream(stream))
+    if rc != DWTFRAG_OK:
+        raise DwtfragError(rc, "dwtfrag_protect_noalloc")
+    return priv, pub
+
+
 def restore(priv: torch.Tensor, pub: torch.Tensor, n: int, width: int, levels: int,
             key: bytes, nonce: bytes, *, out: torch.Tensor | None = None,
             ws: torch.Tensor | None = None, launch=None, stream=None) -> torch.Tensor:
@@ -231,3 +256,4 @@ def aes128_ctr(x: torch.Tensor, key: bytes, nonce: bytes, first_block: int = 0, 
     if rc != DWTFRAG_OK:
         raise DwtfragError(rc, "dwtfrag_aes128_ctr")
     return out
+

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -58,6 +59,9 @@ namespace {
 // unit plus halos (under 64 rows) past the end, so the limit keeps 2^16 below
 // 2^31.
 constexpr uint64_t kMaxDim = 0x7FFF0000ull;
+
+// Bytes of the static workspace behind dwtfrag_protect_noalloc (16 MiB).
+constexpr uint64_t kScratchBytes = uint64_t(16) << 20;
 
 struct Geometry {
   uint64_t n;
@@ -244,6 +248,61 @@ int plan_single_stage(uint64_t n, uint32_t width, uint32_t levels, bool forward,
   *priv_bytes = g.priv_bytes;
   return plan_stage(g, 0, forward, launch, key, P, L, C1, false);
 }
+// Forward stages of a planned geometry: validation of the buffers, key
+// expansion, launch planning and the launches (workspace: g.ws_bytes bytes, or
+// null when that is 0).
+int protect_planned(const Geometry &g, const uint8_t *in, const uint8_t key[16],
+                    const uint8_t nonce[16], uint8_t *priv, int16_t *pub, void *workspace,
+                    const dwtfrag_launch *launch, void *stream) {
+  if (!pub && g.pub_bytes) return DWTFRAG_EINVAL;  // pub may be NULL only when empty
+  if (!aligned16(in) || !aligned16(priv) || !aligned16(pub) || (workspace && !aligned16(workspace)))
+    return DWTFRAG_EINVAL;
+  AesKey k;
+  expand_key(key, nonce, &k);
+  std::vector<StageParams> plans(g.stages);
+  std::vector<int> Ls(g.stages), C1s(g.stages);
+  for (int s = 0; s < g.stages; ++s) {
+    const int rc = plan_stage(g, s, true, launch, k, &plans[s], &Ls[s], &C1s[s], true);
+    if (rc != DWTFRAG_OK) return rc;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int s = 0; s < g.stages; ++s) {
+    const bool last = (s == g.stages - 1);
+    const void *src = (s == 0) ? static_cast<const void *>(in)
+                               : static_cast<const char *>(workspace) + g.ws_off[s - 1];
+    int16_t *dst = last ? reinterpret_cast<int16_t *>(priv)
+                        : reinterpret_cast<int16_t *>(static_cast<char *>(workspace) + g.ws_off[s]);
+    if (launch_fwd(Ls[s], C1s[s], s == 0, src, pub, dst, plans[s], st) != hipSuccess)
+      return DWTFRAG_EDEVICE;
+  }
+  return DWTFRAG_OK;
+}
+
+// Static workspace of dwtfrag_protect_noalloc: one array per device, kept
+// until the process ends.  Its host-side name is not a device address; the
+// device address is looked up once per device (with that device current) and
+// only that address is handed to kernels.  Every call on a device shares the
+// array: each stage writes every element of its LL output before the next
+// stage reads it, so nothing needs clearing, and calls that overlap on one
+// device race on it.
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+int device_scratch(void **out) {
+  constexpr int kDev = 64;
+  static std::mutex mu;
+  static void *ptr[kDev] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDev) return DWTFRAG_EDEVICE;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return DWTFRAG_EDEVICE;
+    ptr[dev] = p;
+  }
+  *out = ptr[dev];
+  return DWTFRAG_OK;
+}
+
 }  // namespace dwtfrag
 
 using namespace dwtfrag;
@@ -286,27 +345,23 @@ int dwtfrag_protect(const uint8_t *in, uint64_t n, uint32_t width, uint32_t leve
   if (rc != DWTFRAG_OK) return rc;
   if (!pub && g.pub_bytes) return DWTFRAG_EINVAL;  // pub may be NULL only when empty
   if (g.ws_bytes && (!workspace || workspace_bytes < g.ws_bytes)) return DWTFRAG_EWORKSPACE;
-  if (!aligned16(in) || !aligned16(priv) || !aligned16(pub) || (workspace && !aligned16(workspace)))
-    return DWTFRAG_EINVAL;
-  AesKey k;
-  expand_key(key, nonce, &k);
-  std::vector<StageParams> plans(g.stages);
-  std::vector<int> Ls(g.stages), C1s(g.stages);
-  for (int s = 0; s < g.stages; ++s) {
-    rc = plan_stage(g, s, true, launch, k, &plans[s], &Ls[s], &C1s[s], true);
+  return protect_planned(g, in, key, nonce, priv, pub, workspace, launch, stream);
+}
+
+int dwtfrag_protect_noalloc(const uint8_t *in, uint64_t n, uint32_t width, uint32_t levels,
+                            const uint8_t key[16], const uint8_t nonce[16], uint8_t *priv,
+                            int16_t *pub, const dwtfrag_launch *launch, void *stream) {
+  if (!in || !key || !nonce || !priv) return DWTFRAG_EINVAL;
+  Geometry g;
+  int rc = make_geometry(n, width, levels, &g);
+  if (rc != DWTFRAG_OK) return rc;
+  if (g.ws_bytes > kScratchBytes) return DWTFRAG_ESCRATCH;
+  void *ws = nullptr;
+  if (g.ws_bytes) {
+    rc = device_scratch(&ws);
     if (rc != DWTFRAG_OK) return rc;
   }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  for (int s = 0; s < g.stages; ++s) {
-    const bool last = (s == g.stages - 1);
-    const void *src = (s == 0) ? static_cast<const void *>(in)
-                               : static_cast<const char *>(workspace) + g.ws_off[s - 1];
-    int16_t *dst = last ? reinterpret_cast<int16_t *>(priv)
-                        : reinterpret_cast<int16_t *>(static_cast<char *>(workspace) + g.ws_off[s]);
-    if (launch_fwd(Ls[s], C1s[s], s == 0, src, pub, dst, plans[s], st) != hipSuccess)
-      return DWTFRAG_EDEVICE;
-  }
-  return DWTFRAG_OK;
+  return protect_planned(g, in, key, nonce, priv, pub, ws, launch, stream);
 }
 
 int dwtfrag_restore(const uint8_t *priv, const int16_t *pub, uint64_t n, uint32_t width,
@@ -432,6 +487,7 @@ const char *dwtfrag_strerror(int code) {
     case DWTFRAG_ERANGE: return "geometry out of range";
     case DWTFRAG_EDEVICE: return "HIP runtime or launch error";
     case DWTFRAG_EWORKSPACE: return "workspace missing or too small";
+    case DWTFRAG_ESCRATCH: return "the transform needs more workspace than the library's 16 MiB static buffer holds";
     default: return "unknown status";
   }
 }

@@ -189,3 +189,17 @@ def test_learned_geometry_pairs_and_limits():
         assert pairs > 0 or (h == 1 and w == 1)
     with pytest.raises(pkg.DwtfragError):
         GL.learned_geometry(100, 10, 4)
+
+
+def test_noalloc_rejects_workspace_above_static_buffer():
+    L = _lib_or_skip()
+    n, width, levels = 1 << 33, 1 << 16, 6
+    assert pkg.geometry(n, width, levels)["workspace_bytes"] > 16 << 20
+    # rejected on the host before any device call: the pointers are never used
+    fake = 1 << 12
+    assert L.dwtfrag_protect_noalloc(fake, n, width, levels, bytes(16), bytes(16), fake, fake,
+                                     None, None) == pkg.DWTFRAG_ESCRATCH
+    assert L.dwtfrag_protect_noalloc(None, n, width, levels, bytes(16), bytes(16), fake, fake,
+                                     None, None) == pkg.DWTFRAG_EINVAL
+    assert "16 MiB" in pkg.strerror(pkg.DWTFRAG_ESCRATCH)
+
