@@ -317,6 +317,53 @@ int dwtfrag_trainer_step(dwtfrag_trainer *state, const int8_t *ctx, const int32_
                          uint64_t count, uint64_t stride, float lr,
                          void *workspace, uint64_t workspace_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * The thesis's own per-8x8-block protection (Ch. 5 section 5.2.1 "Designs";
+ * bit budget of section 5.2.2.2).  The byte matrix (row width a multiple of
+ * 8, rows padded with zeros to a multiple of 8) is cut into 8x8 blocks,
+ * numbered row-major; each gets two levels of the 5/3 lifting (whole-sample
+ * mirror at the block's own edges, rows first).  Per block:
+ *   private record   LL2 (4 x 10 bits)                         40 bits
+ *   first public     HL2, LH2 (10 bits each), HH2 (11 bits)     124 bits
+ *   second public    HL1, LH1, HH1 (48 x 10 bits)               480 bits
+ * values two's complement in their width, bands row-major, records as bit
+ * streams (bit i = bit i % 8 of byte i / 8) laid end to end in block order.
+ * The first public record is XORed with the first 124 bits of
+ *   SHA-256(private record (5 bytes) | key | nonce | block index (8 bytes BE)),
+ * the second with the first 480 bits of
+ *   SHA-512(protected first record (16 bytes, 4 zero bits on top) | key | nonce
+ *           | block index),
+ * and the private fragment is AES-128-CTR(key, nonce) of the concatenated
+ * private records, as dwtfrag_protect's.  Restore writes every sample modulo
+ * 256.  Every device pointer 16-byte aligned (EINVAL otherwise); EINVAL also
+ * for n == 0 or a width that is not a positive multiple of 8.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+  uint64_t n;
+  uint32_t width;
+  uint64_t height;          /* ceil(n / width) */
+  uint64_t block_rows;      /* ceil(height / 8) */
+  uint64_t block_cols;      /* width / 8 */
+  uint64_t blocks;          /* block_rows * block_cols */
+  uint64_t priv_bytes;      /* 5 * blocks */
+  uint64_t pub1_bytes;      /* ceil(124 * blocks / 8) */
+  uint64_t pub2_bytes;      /* 60 * blocks */
+} dwtfrag_se8_geom;
+
+/* Host-only, pure: geometry of the blocked form. */
+int dwtfrag_se8_geometry(uint64_t n, uint32_t width, dwtfrag_se8_geom *out);
+
+/* Forward: in (device, n bytes) -> priv, pub1, pub2 (device, sizes above). */
+int dwtfrag_se8_protect(const uint8_t *in, uint64_t n, uint32_t width,
+                        const uint8_t key[16], const uint8_t nonce[16],
+                        uint8_t *priv, uint8_t *pub1, uint8_t *pub2, void *stream);
+
+/* Inverse: the three fragments -> out (device, n bytes). */
+int dwtfrag_se8_restore(const uint8_t *priv, const uint8_t *pub1, const uint8_t *pub2,
+                        uint64_t n, uint32_t width, const uint8_t key[16],
+                        const uint8_t nonce[16], uint8_t *out, void *stream);
+
 /* Static text for a status code. */
 const char *dwtfrag_strerror(int code);
 

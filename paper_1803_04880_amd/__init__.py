@@ -40,6 +40,13 @@ class _Geom(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_uint64)]
 
 
+class _Se8Geom(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("width", ctypes.c_uint32), ("height", ctypes.c_uint64),
+                ("block_rows", ctypes.c_uint64), ("block_cols", ctypes.c_uint64),
+                ("blocks", ctypes.c_uint64), ("priv_bytes", ctypes.c_uint64),
+                ("pub1_bytes", ctypes.c_uint64), ("pub2_bytes", ctypes.c_uint64)]
+
+
 class Launch(ctypes.Structure):
     """Optional launch shape; zero fields mean the library default."""
     _fields_ = [("seg_rows", ctypes.c_uint32), ("lane_cols", ctypes.c_uint32)]
@@ -55,7 +62,8 @@ EXPORTS = ("dwtfrag_geometry", "dwtfrag_default_width", "dwtfrag_protect",
            "dwtfrag_trainer_step",
            "dwtfrag_batch_create", "dwtfrag_batch_device_bytes", "dwtfrag_batch_upload",
            "dwtfrag_batch_protect", "dwtfrag_batch_restore", "dwtfrag_batch_destroy",
-           "dwtfrag_autotune")
+           "dwtfrag_autotune",
+           "dwtfrag_se8_geometry", "dwtfrag_se8_protect", "dwtfrag_se8_restore")
 
 
 def lib():
@@ -114,6 +122,11 @@ def lib():
                                    ctypes.POINTER(ctypes.c_float), vp]
     for f in ("dwtfrag_batch_create", "dwtfrag_batch_upload", "dwtfrag_batch_protect",
               "dwtfrag_batch_restore", "dwtfrag_autotune"):
+        getattr(L, f).restype = ctypes.c_int
+    L.dwtfrag_se8_geometry.argtypes = [u64, u32, ctypes.POINTER(_Se8Geom)]
+    L.dwtfrag_se8_protect.argtypes = [vp, u64, u32, cp, cp, vp, vp, vp, vp]
+    L.dwtfrag_se8_restore.argtypes = [vp, vp, vp, u64, u32, cp, cp, vp, vp]
+    for f in ("dwtfrag_se8_geometry", "dwtfrag_se8_protect", "dwtfrag_se8_restore"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -257,3 +270,58 @@ def aes128_ctr(x: torch.Tensor, key: bytes, nonce: bytes, first_block: int = 0, 
         raise DwtfragError(rc, "dwtfrag_aes128_ctr")
     return out
 
+
+# ---------------------------------------------------------------------------
+# The per-8x8-block protection (SHA-2 keystreams over the public fragments,
+# 10/11-bit packed records).
+
+def se8_geometry(n: int, width: int) -> dict:
+    g = _Se8Geom()
+    rc = lib().dwtfrag_se8_geometry(n, width, ctypes.byref(g))
+    if rc != DWTFRAG_OK:
+        raise DwtfragError(rc, "dwtfrag_se8_geometry")
+    return {f: getattr(g, f) for f, _ in _Se8Geom._fields_}
+
+
+def se8_protect(x: torch.Tensor, width: int, key: bytes, nonce: bytes, *, out=None, stream=None):
+    """(priv, pub1, pub2) uint8 fragments of the bytes in ``x``; ``out`` may
+    pass the three tensors to fill."""
+    _check_dev(x, torch.uint8, "x")
+    n = x.numel()
+    g = se8_geometry(n, width)
+    sizes = (g["priv_bytes"], g["pub1_bytes"], g["pub2_bytes"])
+    if out is None:
+        out = tuple(torch.empty(s, dtype=torch.uint8, device=x.device) for s in sizes)
+    for t, s, name in zip(out, sizes, ("priv", "pub1", "pub2")):
+        _check_dev(t, torch.uint8, name)
+        if t.numel() != s:
+            raise ValueError(f"{name} holds {t.numel()} bytes, the geometry needs {s}")
+    rc = lib().dwtfrag_se8_protect(x.data_ptr(), n, width, _key16(key, "key"),
+                                   _key16(nonce, "nonce"), out[0].data_ptr(), out[1].data_ptr(),
+                                   out[2].data_ptr(), _stream(stream))
+    if rc != DWTFRAG_OK:
+        raise DwtfragError(rc, "dwtfrag_se8_protect")
+    return tuple(out)
+
+
+def se8_restore(priv: torch.Tensor, pub1: torch.Tensor, pub2: torch.Tensor, n: int, width: int,
+                key: bytes, nonce: bytes, *, out: torch.Tensor | None = None,
+                stream=None) -> torch.Tensor:
+    """The original n bytes from the three fragments."""
+    g = se8_geometry(n, width)
+    for t, s, name in zip((priv, pub1, pub2), (g["priv_bytes"], g["pub1_bytes"], g["pub2_bytes"]),
+                          ("priv", "pub1", "pub2")):
+        _check_dev(t, torch.uint8, name)
+        if t.numel() != s:
+            raise ValueError(f"{name} holds {t.numel()} bytes, the geometry needs {s}")
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint8, device=priv.device)
+    _check_dev(out, torch.uint8, "out")
+    if out.numel() < n:
+        raise ValueError("out holds fewer than n bytes")
+    rc = lib().dwtfrag_se8_restore(priv.data_ptr(), pub1.data_ptr(), pub2.data_ptr(), n, width,
+                                   _key16(key, "key"), _key16(nonce, "nonce"), out.data_ptr(),
+                                   _stream(stream))
+    if rc != DWTFRAG_OK:
+        raise DwtfragError(rc, "dwtfrag_se8_restore")
+    return out

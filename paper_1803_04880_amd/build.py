@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdwtfrag.so")
-SOURCES = ["api.hip", "batch.hip", "fwd.hip", "inv.hip", "ctr.hip", "learned.hip"]
+SOURCES = ["api.hip", "batch.hip", "fwd.hip", "inv.hip", "ctr.hip", "learned.hip", "se8.hip"]
 ARCH = os.environ.get("DWTFRAG_ARCH", "gfx950")
 
 

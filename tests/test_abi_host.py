@@ -203,3 +203,31 @@ def test_noalloc_rejects_workspace_above_static_buffer():
                                      None, None) == pkg.DWTFRAG_EINVAL
     assert "16 MiB" in pkg.strerror(pkg.DWTFRAG_ESCRATCH)
 
+
+@pytest.mark.parametrize("n,width", [(1, 8), (64, 8), (65, 8), (1000, 16), (12345, 96),
+                                     (1 << 28, 32768), (3 * 257 * 64 + 1, 24)])
+def test_se8_geometry_matches_oracle(n, width):
+    _lib_or_skip()
+    from oracle import se8
+    g = pkg.se8_geometry(n, width)
+    o = se8.geometry(n, width)
+    for k in ("height", "block_rows", "block_cols", "blocks", "priv_bytes", "pub1_bytes",
+              "pub2_bytes"):
+        assert g[k] == o[k], k
+
+
+def test_se8_errors_before_launch():
+    L = _lib_or_skip()
+    g = pkg._Se8Geom()
+    assert L.dwtfrag_se8_geometry(0, 8, ctypes.byref(g)) == pkg.DWTFRAG_EINVAL
+    assert L.dwtfrag_se8_geometry(64, 12, ctypes.byref(g)) == pkg.DWTFRAG_EINVAL
+    assert L.dwtfrag_se8_geometry(64, 0, ctypes.byref(g)) == pkg.DWTFRAG_EINVAL
+    assert L.dwtfrag_se8_geometry(64, 8, None) == pkg.DWTFRAG_EINVAL
+    fake = 1 << 12
+    # misaligned or null pointers are rejected on the host
+    assert L.dwtfrag_se8_protect(fake + 8, 64, 8, bytes(16), bytes(16), fake, fake, fake,
+                                 None) == pkg.DWTFRAG_EINVAL
+    assert L.dwtfrag_se8_protect(fake, 64, 8, bytes(16), bytes(16), None, fake, fake,
+                                 None) == pkg.DWTFRAG_EINVAL
+    assert L.dwtfrag_se8_restore(fake, fake, fake + 4, 64, 8, bytes(16), bytes(16), fake,
+                                 None) == pkg.DWTFRAG_EINVAL
