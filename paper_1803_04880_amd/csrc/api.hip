@@ -202,7 +202,7 @@ int plan_stage(const Geometry &g, int s, bool forward, const dwtfrag_launch *lau
   int64_t n_seg;
   if (launch && launch->seg_rows) {
     const int own_h = std::max(unit, round_up(int(std::min<uint32_t>(launch->seg_rows, uint32_t(P->H))), unit));
-    n_seg = (P->H + own_h - 1) / own_h;
+    n_seg = (int64_t(P->H) + own_h - 1) / own_h;
   } else {
     // one round of resident wavefronts: as many segments as fill the device
     // once, each at least two units long (halo work stays below the owned).
