@@ -583,78 +583,146 @@ def run_se8(args):
     print(json.dumps(result), flush=True)
 
 
+def _batch_item(spec):
+    import synth
+    return synth.batch_buffer(spec)
+
+
 def run_batch(args):
     """Uneven batch: --count buffers (default 2048), sizes floor(exp U(ln 2^12,
-    ln 2^26)) and levels U{1..4} from the seeded specs of synth.batch_specs,
-    default widths; contents random bytes from a seeded device generator.
-    Launch shapes are autotuned per (width, levels) class before timing; a
-    step is one batched protect + one batched restore of every buffer."""
+    ln 2^26)), content kinds and levels U{1..4} from the seeded specs of
+    synth.batch_specs, default widths, mixed content from synth.batch_buffer.
+    Rows per tile are autotuned per (width, levels) class before timing.  A
+    step is one batched protect + one batched restore of every buffer, each
+    one persistent kernel launch; the timed steps replay the two directions
+    as captured HIP graphs (eager steps reported beside them)."""
+    import multiprocessing
+
+    import numpy as np
     import torch
 
     import synth
+    from oracle import fragment
     from paper_1803_04880_amd import batch as B
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     specs = synth.batch_specs(args.count)
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(3)
-    xs = [torch.randint(0, 256, (s["n"],), dtype=torch.uint8, device=dev, generator=gen)
-          for s in specs]
+    t0 = time.time()
+    xs = []
+    with multiprocessing.get_context("fork").Pool(_host_cores()) as pool:
+        for buf in pool.imap(_batch_item, specs, chunksize=4):
+            xs.append(torch.from_numpy(buf).to(dev))
     total = sum(s["n"] for s in specs)
-    log(f"{len(specs)} buffers, {total / 1e9:.2f} GB")
+    log(f"{len(specs)} buffers, {total / 1e9:.2f} GB of mixed content in {time.time() - t0:.1f}s")
+    widths = [s["width"] for s in specs]
+    levels = [s["levels"] for s in specs]
+    keys = [np.random.default_rng(s["seed"] + 10**6).bytes(16) for s in specs]
+    nonces = [s["nonce"] for s in specs]
     t0 = time.time()
     tune = {}
     if not args.no_tune:
-        tune = B.tune_classes(xs, [s["width"] for s in specs], [s["levels"] for s in specs])
+        tune = B.tune_classes(xs, widths, levels)
         log(f"tuned {len(tune)} classes in {time.time() - t0:.1f}s: "
             + ", ".join(f"{k}->({v.seg_rows},{v.lane_cols})" for k, v in sorted(tune.items())))
-    b = B.Batch(xs, [s["width"] for s in specs], [s["levels"] for s in specs],
-                [bytes(16)] * len(specs), [s["nonce"] for s in specs], tune=tune)
+    b = B.Batch(xs, widths, levels, keys, nonces, tune=tune)
     b.protect()
     b.restore()
     torch.cuda.synchronize()
     ok = all(bool(torch.equal(o, x)) for o, x in zip(b.outs, xs))
-    stream = torch.cuda.current_stream()
-    steps = args.steps if args.steps != 50 else 5
-    warmup = args.warmup if args.warmup != 5 else 1
+    # fragments of a sample of items against the oracle (the small ones:
+    # the oracle takes seconds per MB)
+    small = sorted(range(len(specs)), key=lambda i: specs[i]["n"])[:6] + [
+        i for i in range(len(specs)) if specs[i]["n"] < (1 << 20)][-2:]
+    for i in small:
+        buf = xs[i].cpu().numpy()
+        opriv, opub = fragment.protect(buf, widths[i], levels[i], keys[i], nonces[i])
+        ok &= b.privs[i].cpu().numpy().tobytes() == opriv
+        ok &= b.pubs[i].cpu().numpy().tobytes() == opub
+    log(f"batch: round trip of every item and {len(small)} items' fragments vs oracle: "
+        f"{'exact' if ok else 'MISMATCH'}")
+    steps = args.steps if args.steps != 50 else 10
+    warmup = args.warmup if args.warmup != 5 else 2
     for _ in range(warmup):
         b.protect()
         b.restore()
     torch.cuda.synchronize()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
-    w0 = time.perf_counter()
-    for k in range(steps):
-        ev[k][0].record(stream)
-        b.protect()
-        ev[k][1].record(stream)
-        b.restore()
-        ev[k][2].record(stream)
+    stream = torch.cuda.current_stream()
+
+    def timed(fp, fr):
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for k in range(steps):
+            ev[k][0].record(stream)
+            fp()
+            ev[k][1].record(stream)
+            fr()
+            ev[k][2].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        tp = [ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]
+        tr = [ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]
+        return wall, tp, tr
+
+    wall_e, tp_e, tr_e = timed(b.protect, b.restore)
+    # each direction captured as a HIP graph of its one launch, replayed
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    gp, gr = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(gp, stream=side):
+            b.protect(stream=side)
+        with torch.cuda.graph(gr, stream=side):
+            b.restore(stream=side)
+    stream.wait_stream(side)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    tp = [ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]
-    tr = [ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]
-    alg = 3 * total + 3 * total   # about 3 B per element each way
-    pair_ms = (sum(tp) + sum(tr)) / steps
+    gp.replay()
+    gr.replay()
+    torch.cuda.synchronize()
+    ok &= all(bool(torch.equal(o, x)) for o, x in zip(b.outs, xs))
+    wall, tp, tr = timed(gp.replay, gr.replay)
+    torch.cuda.synchronize()
+    ok &= all(bool(torch.equal(o, x)) for o, x in zip(b.outs, xs))
+    alg = sum(s["n"] + 2 * (-(-s["n"] // s["width"])) * s["width"] for s in specs)  # per direction
+    avg_p, avg_r = sum(tp) / steps, sum(tr) / steps
+    dom = "fwd_batch_kernel" if avg_p >= avg_r else "inv_batch_kernel"
+    dom_ms = max(avg_p, avg_r)
     result = {
         "metric": "batched protect+restore GB/s on 1 MI355X, bit-exact",
         "value": round(total * steps / wall / 1e9, 2), "unit": "GB/s", "n_gpus": 1, "steps": steps,
         "warmup": warmup, "ms_per_step": round(wall / steps * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int16/int32", "data": "synthetic",
-        "config": {"workload": f"{len(specs)} uneven buffers ({total / 1e9:.2f} GB), 1-4 levels, "
-                               + ("default tile shapes" if args.no_tune else
-                                  "tile shape per (width, levels) class tuned on batched runs"),
+        "config": {"workload": f"{len(specs)} uneven buffers ({total / 1e9:.2f} GB, mixed content), "
+                               "1-4 levels, one persistent launch per direction replayed as HIP graphs, "
+                               + ("default tile heights" if args.no_tune else
+                                  "tile heights tuned per (width, levels) class"),
                    "buffers": len(specs), "bytes": total, "classes": len(tune)},
-        "bit_exact_roundtrip": ok,
+        "bit_exact": ok,
         "latency_ms": {"protect_p50": round(percentile(tp, 50), 3),
                        "restore_p50": round(percentile(tr, 50), 3)},
-        "roofline": {"bound": "hbm", "achieved": round(alg / (pair_ms * 1e-3) / 1e9, 1),
+        "eager": {"value": round(total * steps / wall_e / 1e9, 2),
+                  "protect_p50_ms": round(percentile(tp_e, 50), 3),
+                  "restore_p50_ms": round(percentile(tr_e, 50), 3)},
+        "roofline": {"bound": "hbm", "achieved": round(alg / (dom_ms * 1e-3) / 1e9, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(alg / (pair_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "all batch launches of protect+restore"},
+                     "frac": round(alg / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": dom, "bytes_per_launch": alg, "avg_launch_ms": round(dom_ms, 3)},
         "cpu_baseline": None,
     }
     print(json.dumps(result), flush=True)
+
+
+def _launch_stats(log):
+    """p50 / p99 / max of launch -> retire (host clock) over the server's
+    launches, with the requests and bytes of the slowest."""
+    if not log:
+        return None
+    d = [(r - l) * 1e3 for l, r, _, _ in log]
+    worst = max(range(len(log)), key=lambda i: d[i])
+    return {"p50": round(percentile(d, 50), 3), "p99": round(percentile(d, 99), 3),
+            "max": round(d[worst], 3), "max_at_s": round(log[worst][0], 3),
+            "max_requests": log[worst][2], "max_bytes": log[worst][3]}
 
 
 def run_serve(args):
@@ -715,6 +783,7 @@ def run_serve(args):
         r.out_priv = r.out_pub = r.out = None
 
     srv.on_complete = on_complete
+    srv.warmup()
     wall = srv.run(reqs)
     lat = [(r.done - r.arrival) * 1e3 for r in reqs]
     total = sum(r.n for r in reqs)
@@ -732,6 +801,7 @@ def run_serve(args):
         "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),
                        "max": round(max(lat), 3)},
         "launches": srv.batches_launched, "wall_s": round(wall, 3),
+        "launch_to_retire_ms": _launch_stats(srv.launch_log),
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(result), flush=True)
@@ -866,9 +936,12 @@ def run_learned(args):
     wall, tp, tr = timed(lambda: protect_all(gold_net), lambda: restore_all(gold_net))
     total = n * nimg
     value = total * steps / wall / 1e9
-    # ALU roofline of the learned passes: int8 multiply-accumulates of the
-    # network (8x16 + 16 per predicted sample) over all predict steps of both
-    # directions, against the v_dot4 rate (4 MACs per lane per cycle)
+    # Roofline of the learned passes: int8 multiply-accumulates of the network
+    # (8x16 + 16 per predicted sample) over all predict steps of both
+    # directions, as operations (2 per MAC) against the dense int8 matrix-core
+    # peak (5.0 POP/s), with the VALU v_dot4 rate (4 MACs per lane per cycle)
+    # and the HBM fraction of the algorithmic bytes (3 per element each way)
+    # beside it
     _, pairs = GL.learned_geometry(n, W, L)
     macs = 2 * pairs * 144 * nimg
     pair_us = (sum(tp) + sum(tr)) / steps
@@ -893,10 +966,13 @@ def run_learned(args):
         "training": {"pairs": int(tgt.numel()), "steps": 300, "seconds": round(train_s, 3),
                      "final_batch_loss": round(float(st.loss), 4),
                      "oracle_loss_end_full_set": rec["loss_end"]},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 1),
-                     "unit": "TMAC/s (int8 dot4)", "frac": round(achieved / peak, 4),
+        "roofline": {"bound": "mfma", "achieved": round(2 * achieved, 3), "peak": 5000.0,
+                     "unit": "T int8 ops/s (multiply and add)",
+                     "frac": round(2 * achieved / 5000.0, 5),
                      "traffic": None, "kernel": "all learned passes of protect+restore",
-                     "macs_per_step": macs},
+                     "macs_per_step": macs,
+                     "valu_dot4_frac": round(achieved / peak, 4),
+                     "hbm_frac": round(2 * (n + 2 * n) * nimg / (pair_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
         "cpu_baseline": None,
     }
     print(json.dumps(result), flush=True)

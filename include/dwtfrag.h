@@ -156,11 +156,13 @@ int dwtfrag_aes128_ctr(const uint8_t *in, uint8_t *out, uint64_t nbytes,
  * Batches of independent buffers (the thesis cuts data into many fixed-size
  * chunks, Ch. 5 section 5.2.1, and feeds many chunks per GPU call).  A batch
  * is planned once on the host, copied into a caller-owned device buffer, and
- * run by persistent launches that drain one tile queue per kernel shape, so
- * buffers of uneven sizes share the device.  Each item's fragments are
- * exactly those of dwtfrag_protect on that item alone.  The run calls launch
- * kernels only (no allocation, copy or memset): they can be captured in a
- * HIP graph and replayed.  Calls on one plan must be ordered on one stream.
+ * run by one persistent launch per direction that drains a single tile queue
+ * (every item's tiles, longest first, 16 columns per lane), so buffers of
+ * uneven sizes and depths share the device in one kernel.  Each item's
+ * fragments are exactly those of dwtfrag_protect on that item alone.  The
+ * run calls launch one kernel each (no allocation, copy or memset; the
+ * kernels leave their queue counters reset): they can be captured in a HIP
+ * graph and replayed.  Calls on one plan must be ordered on one stream.
  * ------------------------------------------------------------------------ */
 
 typedef struct {
@@ -185,11 +187,12 @@ typedef struct {
 typedef struct dwtfrag_batch dwtfrag_batch;  /* opaque host-side plan */
 
 /* Host only: plan `count` items (host array, read before return).  Items of a
- * (width, levels) class listed in `tune` use that launch shape, others
- * 128-row tiles.  *out receives a plan owned by the caller (free it with
- * dwtfrag_batch_destroy).  EINVAL for a null or misaligned pointer, levels
- * outside 1..4; ERANGE for geometry out of range or more than 8 kernel
- * shapes. */
+ * (width, levels) class listed in `tune` use that entry's rows per tile,
+ * others 128-row tiles; batch tiles always have 16 columns per lane (the
+ * entry's lane_cols must be 0, 8 or 16 and is not otherwise used).  *out
+ * receives a plan owned by the caller (free it with dwtfrag_batch_destroy).
+ * EINVAL for a null or misaligned pointer, levels outside 1..4 or a bad
+ * lane_cols; ERANGE for geometry out of range. */
 int dwtfrag_batch_create(const dwtfrag_item *items, uint32_t count,
                          const dwtfrag_tune_entry *tune, uint32_t n_tune,
                          dwtfrag_batch **out);

@@ -1,9 +1,9 @@
 """Batches of independent buffers and the launch-shape autotuner (ctypes).
 
 A batch is planned once (``dwtfrag_batch_create``), its tables are copied
-into a device tensor, and every protect / restore of the batch is a handful
-of kernel launches (persistent drains of one tile queue per kernel shape),
-which can be captured in a HIP graph and replayed.  Marshalling only.
+into a device tensor, and every protect / restore of the batch is one
+persistent kernel launch draining one tile queue, which can be captured in a
+HIP graph and replayed.  Marshalling only.
 
     b = Batch(buffers, widths, levels, keys, nonces)
     b.protect(); b.restore()          # b.privs / b.pubs / b.outs hold results
@@ -46,11 +46,12 @@ def autotune(x: torch.Tensor, width: int, levels: int, trials: int = 3, stream=N
 
 
 def tune_classes(buffers, widths, levels, trials: int = 2,
-                 candidates=((64, 8), (128, 8), (256, 8), (128, 16), (256, 16)), stream=None):
+                 candidates=((64, 16), (128, 16), (256, 16)), stream=None):
     """Batch autotuner: for every (width, levels) class of the buffers, time a
     batched protect + restore of that class's buffers under each candidate
-    tile shape (rows per tile, columns per lane) with HIP events and keep the
-    fastest.  Returns {(width, levels): Launch} for ``Batch(tune=...)``.
+    tile shape (rows per tile, columns per lane; batch tiles always have 16
+    columns per lane) with HIP events and keep the fastest.  Returns
+    {(width, levels): Launch} for ``Batch(tune=...)``.
 
     Unlike ``autotune`` (one buffer alone, where finer tiles fill the device),
     this times the shapes where they will run: many buffers per launch, where
@@ -64,8 +65,6 @@ def tune_classes(buffers, widths, levels, trials: int = 2,
         xs = [buffers[i] for i in idx]
         best = None
         for rows, cols in candidates:
-            if key[1] % 4 == 0 and cols == 8:
-                continue   # a four-level stage needs 16 columns per lane
             b = Batch(xs, [key[0]] * len(xs), [key[1]] * len(xs), [bytes(16)] * len(xs),
                       [bytes(16)] * len(xs), tune={key: (rows, cols)})
             b.protect(stream=st)

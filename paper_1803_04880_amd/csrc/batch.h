@@ -2,16 +2,21 @@
 // many chunks in one go: the thesis cuts data into many equal chunks, Ch. 5
 // section 5.2.1, and its GPU runs take many chunks as input).
 //
-// Each buffer ("item") is one fused stage (levels <= 4).  Items are grouped
-// into classes of equal kernel shape (levels, columns per lane); a class's
-// tiles (item, wavefront index within the item) form one queue that a
-// persistent launch drains with an atomic head counter, so uneven buffers
-// share the device without a tail per buffer.
+// Each buffer ("item") is one fused stage (levels <= 4) planned with 16
+// columns per lane, the layout every depth up to four levels can use, so one
+// kernel per direction serves all items: its tiles (item, wavefront index
+// within the item) form a single queue, longest first, that one persistent
+// launch drains with an atomic head counter, dispatching each tile on its
+// item's depth.  The last workgroup to finish resets the counters, so a
+// batch direction is exactly one kernel launch.
 #pragma once
 
 #include "common.h"
 
 namespace dwtfrag {
+
+// Columns per lane of every batch tile.
+constexpr int kBatchCols = 16;
 
 struct BatchItem {
   StageParams fwd;     // forward plan (halo shape of the forward kernel)
@@ -21,16 +26,28 @@ struct BatchItem {
   int16_t *pub;        // public fragment (device)
   uint8_t *out;        // restore output (device)
   uint64_t priv_bytes; // 2 * h_L * w_L
+  int32_t levels;      // 1..4
+  int32_t pad;
 };
 
-// Tile queue head counters, reset by a kernel before every drain: one per
-// class and direction.
-constexpr int kBatchClasses = 8;
-
-struct BatchClass {
-  int L, C1;
-  int64_t n_tiles;
-  int64_t tile_off;    // first tile of the class in the tile array
+// Queue counters of one direction: [0] next tile, [1] finished workgroups.
+struct BatchCounters {
+  unsigned int head, done;
 };
+
+// Called by every workgroup once its wavefronts have left the tile loop: the
+// last one resets both counters for the next launch (no other workgroup pops
+// a tile any more at that point).
+__device__ __forceinline__ void batch_finish(BatchCounters *c) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned int d = atomicAdd(&c->done, 1u);
+    if (d == gridDim.x - 1) {
+      atomicExch(&c->head, 0u);
+      atomicExch(&c->done, 0u);
+    }
+  }
+}
 
 }  // namespace dwtfrag

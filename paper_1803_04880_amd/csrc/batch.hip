@@ -2,12 +2,13 @@
 //
 // The thesis cuts data into many fixed-size chunks (Ch. 5 section 5.2.1) and
 // its GPU runs take many chunks per call.  Here a batch is planned once on the
-// host (every item's geometry and launch plan, grouped into classes of equal
-// kernel shape, with one tile list per class), copied into a caller-owned
-// device buffer, and then run by persistent launches that drain each class's
-// tile queue: protect = forward drains (encryption fused), restore = inverse
-// drains (decryption fused).  The run calls launch kernels only, so they can
-// be captured in a HIP graph.
+// host (every item's geometry and launch plan with 16 columns per lane, and
+// one tile list per direction, longest tiles first), copied into a
+// caller-owned device buffer, and then run by one persistent launch per
+// direction that drains the direction's queue: protect = the forward drain
+// (encryption fused), restore = the inverse drain (decryption fused).  The
+// kernels reset their own queue counters when they finish, so a direction is
+// one kernel launch and can be captured in a HIP graph.
 #include "dwtfrag.h"
 
 #include <algorithm>
@@ -20,20 +21,15 @@
 
 namespace dwtfrag {
 
-hipError_t launch_fwd_batch(int L, int C1, const BatchItem *items, const int2 *tiles, int64_t n_tiles,
-                            unsigned int *head, int blocks, hipStream_t s);
-hipError_t launch_inv_batch(int L, int C1, const BatchItem *items, const int2 *tiles, int64_t n_tiles,
-                            unsigned int *head, int blocks, hipStream_t s);
-int fwd_waves_per_cu(int L, int C1, bool u8in);
-int inv_waves_per_cu(int L, int C1, bool u8out);
+hipError_t launch_fwd_batch(const BatchItem *items, const int2 *tiles, int64_t n_tiles,
+                            BatchCounters *ctr, int blocks, hipStream_t s);
+hipError_t launch_inv_batch(const BatchItem *items, const int2 *tiles, int64_t n_tiles,
+                            BatchCounters *ctr, int blocks, hipStream_t s);
+int fwd_batch_blocks_per_cu();
+int inv_batch_blocks_per_cu();
 int plan_single_stage(uint64_t n, uint32_t width, uint32_t levels, bool forward,
                       const dwtfrag_launch *launch, const AesKey &key, StageParams *P, int *L,
                       int *C1, uint64_t *priv_bytes);
-
-__global__ void reset_heads_kernel(unsigned int *heads, int n) {
-  const int i = int(threadIdx.x);
-  if (i < n) heads[i] = 0u;
-}
 
 }  // namespace dwtfrag
 
@@ -42,10 +38,10 @@ using namespace dwtfrag;
 struct dwtfrag_batch {
   uint32_t count = 0;
   std::vector<BatchItem> items;
-  std::vector<int2> tiles;                 // forward classes, then inverse classes
-  std::vector<BatchClass> fwd_cls, inv_cls;
-  std::vector<int> fwd_blocks, inv_blocks; // persistent grid per class
-  uint64_t off_items = 0, off_tiles = 0, off_heads = 0, bytes = 0;
+  std::vector<int2> tiles;                 // forward queue, then inverse queue
+  int64_t n_fwd = 0, n_inv = 0;            // tiles per direction
+  int fwd_blocks = 0, inv_blocks = 0;      // persistent grid per direction
+  uint64_t off_ctr = 0, off_items = 0, off_tiles = 0, bytes = 0;
   char *dev = nullptr;                     // caller's device copy, set by upload
 };
 
@@ -60,20 +56,13 @@ const dwtfrag_launch *tuned_launch(const dwtfrag_tune_entry *tune, uint32_t n_tu
   return nullptr;
 }
 
-int class_index(std::vector<BatchClass> &cls, int L, int C1) {
-  for (size_t i = 0; i < cls.size(); ++i)
-    if (cls[i].L == L && cls[i].C1 == C1) return int(i);
-  cls.push_back(BatchClass{L, C1, 0, 0});
-  return int(cls.size()) - 1;
-}
-
-int persistent_blocks(bool forward, int L, int C1) {
+// Persistent grid of a batch kernel: resident workgroups per CU x CUs.
+int persistent_blocks(int per_cu) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) dev = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
     cus = 256;
-  const int per_cu = forward ? fwd_waves_per_cu(L, C1, true) : inv_waves_per_cu(L, C1, true);
-  return cus * std::max(1, per_cu / kWavesPerBlock);
+  return cus * std::max(1, per_cu);
 }
 
 }  // namespace
@@ -89,8 +78,8 @@ int dwtfrag_batch_create(const dwtfrag_item *items, uint32_t count, const dwtfra
   if (!b) return DWTFRAG_ERANGE;
   b->count = count;
   b->items.resize(count);
-  // per class: tiles (item, wavefront) of every member item, in item order
-  std::vector<std::vector<int2>> ft, it;
+  // tiles (item, wavefront) of every item, one list per direction
+  std::vector<int2> ft, it;
   for (uint32_t i = 0; i < count; ++i) {
     const dwtfrag_item &src = items[i];
     if (!src.in || !src.priv || src.levels == 0 || src.levels > uint32_t(kMaxFused)) {
@@ -102,18 +91,23 @@ int dwtfrag_batch_create(const dwtfrag_item *items, uint32_t count, const dwtfra
       delete b;
       return DWTFRAG_EINVAL;
     }
-    dwtfrag_launch def{128, 0};  // batches fill the device with many items: 128-row tiles
-    const dwtfrag_launch *ln = tuned_launch(tune, n_tune, src.width, src.levels);
-    if (!ln) ln = &def;
+    // batches fill the device with many items: 128-row tiles unless tuned;
+    // every tile has kBatchCols columns per lane (one kernel serves all depths)
+    const dwtfrag_launch *tl = tuned_launch(tune, n_tune, src.width, src.levels);
+    if (tl && tl->lane_cols != 0 && tl->lane_cols != 8 && tl->lane_cols != 16) {
+      delete b;
+      return DWTFRAG_EINVAL;
+    }
+    const dwtfrag_launch ln{tl && tl->seg_rows ? tl->seg_rows : 128u, uint32_t(kBatchCols)};
     AesKey key;
     expand_key(src.key, src.nonce, &key);
     BatchItem &bi = b->items[i];
     std::memset(&bi, 0, sizeof(bi));
     int Lf = 0, Cf = 0, Li = 0, Ci = 0;
     uint64_t priv_bytes = 0;
-    int rc = plan_single_stage(src.n, src.width, src.levels, true, ln, key, &bi.fwd, &Lf, &Cf, &priv_bytes);
+    int rc = plan_single_stage(src.n, src.width, src.levels, true, &ln, key, &bi.fwd, &Lf, &Cf, &priv_bytes);
     if (rc == DWTFRAG_OK)
-      rc = plan_single_stage(src.n, src.width, src.levels, false, ln, key, &bi.inv, &Li, &Ci, &priv_bytes);
+      rc = plan_single_stage(src.n, src.width, src.levels, false, &ln, key, &bi.inv, &Li, &Ci, &priv_bytes);
     if (rc != DWTFRAG_OK) {
       delete b;
       return rc;
@@ -128,20 +122,13 @@ int dwtfrag_batch_create(const dwtfrag_item *items, uint32_t count, const dwtfra
     bi.pub = src.pub;
     bi.out = src.out;
     bi.priv_bytes = priv_bytes;
-    const int cf = class_index(b->fwd_cls, Lf, Cf);
-    const int ci = class_index(b->inv_cls, Li, Ci);
-    if (int(b->fwd_cls.size()) > kBatchClasses || int(b->inv_cls.size()) > kBatchClasses) {
-      delete b;
-      return DWTFRAG_ERANGE;
-    }
-    ft.resize(b->fwd_cls.size());
-    it.resize(b->inv_cls.size());
-    for (int w = 0; w < bi.fwd.n_waves; ++w) ft[cf].push_back(make_int2(int(i), w));
-    for (int w = 0; w < bi.inv.n_waves; ++w) it[ci].push_back(make_int2(int(i), w));
+    bi.levels = int32_t(src.levels);
+    for (int w = 0; w < bi.fwd.n_waves; ++w) ft.push_back(make_int2(int(i), w));
+    for (int w = 0; w < bi.inv.n_waves; ++w) it.push_back(make_int2(int(i), w));
   }
-  // Longest tiles first within a queue, so the short tiles of small items
-  // fill the end of a drain instead of extending it.  A tile's cost is the
-  // rows it streams (segment plus halos) times the columns of its window.
+  // Longest tiles first, so the short tiles of small items fill the end of a
+  // drain instead of extending it.  A tile's cost is the rows it streams
+  // (segment plus halos) times the columns of its window.
   const auto tile_cost = [](const StageParams &P) {
     const int64_t seg = int64_t(P.unit_rows) * ((P.units + P.n_seg - 1) / P.n_seg);
     return std::min<int64_t>(P.H, seg + P.halo_t + P.halo_b) * std::min(P.W, P.own_w);
@@ -151,28 +138,20 @@ int dwtfrag_batch_create(const dwtfrag_item *items, uint32_t count, const dwtfra
     fcost[i] = tile_cost(b->items[i].fwd);
     icost[i] = tile_cost(b->items[i].inv);
   }
-  for (auto &v : ft)
-    std::stable_sort(v.begin(), v.end(), [&](const int2 &x, const int2 &y) { return fcost[x.x] > fcost[y.x]; });
-  for (auto &v : it)
-    std::stable_sort(v.begin(), v.end(), [&](const int2 &x, const int2 &y) { return icost[x.x] > icost[y.x]; });
-  for (size_t c = 0; c < b->fwd_cls.size(); ++c) {
-    b->fwd_cls[c].tile_off = int64_t(b->tiles.size());
-    b->fwd_cls[c].n_tiles = int64_t(ft[c].size());
-    b->tiles.insert(b->tiles.end(), ft[c].begin(), ft[c].end());
-    b->fwd_blocks.push_back(persistent_blocks(true, b->fwd_cls[c].L, b->fwd_cls[c].C1));
-  }
-  for (size_t c = 0; c < b->inv_cls.size(); ++c) {
-    b->inv_cls[c].tile_off = int64_t(b->tiles.size());
-    b->inv_cls[c].n_tiles = int64_t(it[c].size());
-    b->tiles.insert(b->tiles.end(), it[c].begin(), it[c].end());
-    b->inv_blocks.push_back(persistent_blocks(false, b->inv_cls[c].L, b->inv_cls[c].C1));
-  }
-  if (b->tiles.size() > 0x7fffffffull) {
+  std::stable_sort(ft.begin(), ft.end(), [&](const int2 &x, const int2 &y) { return fcost[x.x] > fcost[y.x]; });
+  std::stable_sort(it.begin(), it.end(), [&](const int2 &x, const int2 &y) { return icost[x.x] > icost[y.x]; });
+  if (ft.size() + it.size() > 0x7fffffffull) {
     delete b;
     return DWTFRAG_ERANGE;
   }
-  b->off_heads = 0;
-  b->off_items = a256(2 * kBatchClasses * sizeof(unsigned int));
+  b->n_fwd = int64_t(ft.size());
+  b->n_inv = int64_t(it.size());
+  b->tiles = std::move(ft);
+  b->tiles.insert(b->tiles.end(), it.begin(), it.end());
+  b->fwd_blocks = persistent_blocks(fwd_batch_blocks_per_cu());
+  b->inv_blocks = persistent_blocks(inv_batch_blocks_per_cu());
+  b->off_ctr = 0;
+  b->off_items = a256(2 * sizeof(BatchCounters));
   b->off_tiles = a256(b->off_items + count * sizeof(BatchItem));
   b->bytes = a256(b->off_tiles + b->tiles.size() * sizeof(int2));
   *out = b;
@@ -186,7 +165,11 @@ int dwtfrag_batch_upload(dwtfrag_batch *b, void *device_plan, uint64_t device_by
   if (device_bytes < b->bytes) return DWTFRAG_EWORKSPACE;
   char *dev = static_cast<char *>(device_plan);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  // pageable sources: the copies are staged before the calls return
+  // pageable sources: the copies are staged before the calls return; the
+  // queue counters start at zero (the kernels leave them at zero)
+  static const BatchCounters zero[2] = {};
+  if (hipMemcpyAsync(dev + b->off_ctr, zero, sizeof(zero), hipMemcpyHostToDevice, st) != hipSuccess)
+    return DWTFRAG_EDEVICE;
   if (hipMemcpyAsync(dev + b->off_items, b->items.data(), b->items.size() * sizeof(BatchItem),
                      hipMemcpyHostToDevice, st) != hipSuccess)
     return DWTFRAG_EDEVICE;
@@ -201,19 +184,13 @@ int dwtfrag_batch_upload(dwtfrag_batch *b, void *device_plan, uint64_t device_by
 
 int dwtfrag_batch_protect(const dwtfrag_batch *b, void *stream) {
   if (!b || !b->dev) return DWTFRAG_EINVAL;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  unsigned int *heads = reinterpret_cast<unsigned int *>(b->dev + b->off_heads);
+  if (b->n_fwd == 0) return DWTFRAG_OK;
+  BatchCounters *ctr = reinterpret_cast<BatchCounters *>(b->dev + b->off_ctr);
   const BatchItem *items = reinterpret_cast<const BatchItem *>(b->dev + b->off_items);
   const int2 *tiles = reinterpret_cast<const int2 *>(b->dev + b->off_tiles);
-  hipLaunchKernelGGL(reset_heads_kernel, dim3(1), dim3(64), 0, st, heads, 2 * kBatchClasses);
-  if (hipGetLastError() != hipSuccess) return DWTFRAG_EDEVICE;
-  for (size_t c = 0; c < b->fwd_cls.size(); ++c) {
-    const BatchClass &k = b->fwd_cls[c];
-    if (k.n_tiles == 0) continue;
-    const int blocks = int(std::min<int64_t>(b->fwd_blocks[c], (k.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock));
-    if (launch_fwd_batch(k.L, k.C1, items, tiles + k.tile_off, k.n_tiles, heads + c, blocks, st) != hipSuccess)
-      return DWTFRAG_EDEVICE;
-  }
+  const int blocks = int(std::min<int64_t>(b->fwd_blocks, (b->n_fwd + kWavesPerBlock - 1) / kWavesPerBlock));
+  if (launch_fwd_batch(items, tiles, b->n_fwd, ctr, blocks, static_cast<hipStream_t>(stream)) != hipSuccess)
+    return DWTFRAG_EDEVICE;
   return DWTFRAG_OK;
 }
 
@@ -221,20 +198,13 @@ int dwtfrag_batch_restore(const dwtfrag_batch *b, void *stream) {
   if (!b || !b->dev) return DWTFRAG_EINVAL;
   for (const BatchItem &i : b->items)
     if (!i.out) return DWTFRAG_EINVAL;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  unsigned int *heads = reinterpret_cast<unsigned int *>(b->dev + b->off_heads);
+  if (b->n_inv == 0) return DWTFRAG_OK;
+  BatchCounters *ctr = reinterpret_cast<BatchCounters *>(b->dev + b->off_ctr) + 1;
   const BatchItem *items = reinterpret_cast<const BatchItem *>(b->dev + b->off_items);
-  const int2 *tiles = reinterpret_cast<const int2 *>(b->dev + b->off_tiles);
-  hipLaunchKernelGGL(reset_heads_kernel, dim3(1), dim3(64), 0, st, heads, 2 * kBatchClasses);
-  if (hipGetLastError() != hipSuccess) return DWTFRAG_EDEVICE;
-  for (size_t c = 0; c < b->inv_cls.size(); ++c) {
-    const BatchClass &k = b->inv_cls[c];
-    if (k.n_tiles == 0) continue;
-    const int blocks = int(std::min<int64_t>(b->inv_blocks[c], (k.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock));
-    if (launch_inv_batch(k.L, k.C1, items, tiles + k.tile_off, k.n_tiles, heads + kBatchClasses + c,
-                         blocks, st) != hipSuccess)
-      return DWTFRAG_EDEVICE;
-  }
+  const int2 *tiles = reinterpret_cast<const int2 *>(b->dev + b->off_tiles) + b->n_fwd;
+  const int blocks = int(std::min<int64_t>(b->inv_blocks, (b->n_inv + kWavesPerBlock - 1) / kWavesPerBlock));
+  if (launch_inv_batch(items, tiles, b->n_inv, ctr, blocks, static_cast<hipStream_t>(stream)) != hipSuccess)
+    return DWTFRAG_EDEVICE;
   return DWTFRAG_OK;
 }
 

@@ -174,12 +174,21 @@ struct StageParams {
   int32_t unit_rows, units;   // 2^L, ceil(H / 2^L)
   int32_t n_seg;              // number of row segments
   int32_t halo_l;             // columns before the owned range (multiple of lane_cols)
+  int32_t last_base;          // first column of the last window's lanes (n_win > 1)
   int32_t halo_t, halo_b;     // rows streamed before / after the owned range
   int32_t n_waves;
   int32_t use_aes;            // LL output / input goes through AES-CTR
   int32_t ks_rows, ks_blocks; // keystream ring: rows per refill, blocks per row
   AesKey key;
 };
+
+// First level-0 column of window win's lanes: the owned range minus the left
+// halo, from column 0 for the first window; the last window's lanes may start
+// further left (last_base) so that they end inside the row.
+__device__ __forceinline__ int window_base(const StageParams &P, int win) {
+  if (win == 0) return 0;
+  return win == P.n_win - 1 ? P.last_base : win * P.own_w - P.halo_l;
+}
 
 // First level-0 row of segment s (s == n_seg gives units * unit_rows).
 __device__ __forceinline__ int seg_start(const StageParams &P, int s) {

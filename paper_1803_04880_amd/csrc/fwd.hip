@@ -664,15 +664,34 @@ static hipError_t launch_fwd_t(const void *in, int16_t *pub, int16_t *llout, con
   return hipGetLastError();
 }
 
-// Batch form: a persistent launch drains one class's tile queue; each tile
-// is one wavefront rectangle of one item (the item's own plan and buffers).
-template <int L, int C1>
+// Batch form: one persistent launch drains the batch's tile queue; each tile
+// is one wavefront rectangle of one item (the item's own plan, buffers and
+// keys), run by the streaming code of the item's depth.
+template <int L> using FwdB = FwdWave<L, kBatchCols, true>;
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int kFwdBatchLds = cmax(cmax(FwdB<1>::kLdsWords, FwdB<2>::kLdsWords),
+                                  cmax(FwdB<3>::kLdsWords, FwdB<4>::kLdsWords));
+
+template <int L>
+__device__ __forceinline__ void fwd_batch_tile(const BatchItem &it, int wave, uint32_t *lds,
+                                               const uint32_t *te, const uint32_t *kw, int lane) {
+  FwdB<L> w{it.fwd};
+  w.te = te;
+  w.kw = kw;
+  w.in8 = it.in;
+  w.in16 = nullptr;
+  w.pub = it.pub;
+  w.llout = reinterpret_cast<int16_t *>(it.priv);
+  w.lds = lds;
+  w.lane = lane;
+  w.run(wave);
+}
+
 __global__ __launch_bounds__(kBlockThreads) void fwd_batch_kernel(const BatchItem *__restrict__ items,
                                                                   const int2 *__restrict__ tiles,
                                                                   int64_t n_tiles,
-                                                                  unsigned int *__restrict__ head) {
-  using W = FwdWave<L, C1, true>;
-  __shared__ uint32_t s_lds[kWavesPerBlock][W::kLdsWords];
+                                                                  BatchCounters *__restrict__ ctr) {
+  __shared__ uint32_t s_lds[kWavesPerBlock][kFwdBatchLds];
   __shared__ uint32_t s_te[1024];
   __shared__ uint32_t s_kw[kWavesPerBlock][kKeyWords];
   load_aes_te(s_te);
@@ -681,39 +700,38 @@ __global__ __launch_bounds__(kBlockThreads) void fwd_batch_kernel(const BatchIte
   const int lane = threadIdx.x & 63;
   for (;;) {
     unsigned int t = 0;
-    if (lane == 0) t = atomicAdd(head, 1u);
+    if (lane == 0) t = atomicAdd(&ctr->head, 1u);
     t = __builtin_amdgcn_readfirstlane(t);
     if (int64_t(t) >= n_tiles) break;
     const int2 e = tiles[t];
     const BatchItem &it = items[e.x];
     if (lane < kKeyWords) s_kw[wib][lane] = key_word(it.fwd.key, lane);  // this item's keys
     wave_lds_sync();
-    W w{it.fwd};
-    w.te = s_te;
-    w.kw = s_kw[wib];
-    w.in8 = it.in;
-    w.in16 = nullptr;
-    w.pub = it.pub;
-    w.llout = reinterpret_cast<int16_t *>(it.priv);
-    w.lds = s_lds[wib];
-    w.lane = lane;
-    w.run(e.y);
+    switch (__builtin_amdgcn_readfirstlane(it.levels)) {
+      case 1: fwd_batch_tile<1>(it, e.y, s_lds[wib], s_te, s_kw[wib], lane); break;
+      case 2: fwd_batch_tile<2>(it, e.y, s_lds[wib], s_te, s_kw[wib], lane); break;
+      case 3: fwd_batch_tile<3>(it, e.y, s_lds[wib], s_te, s_kw[wib], lane); break;
+      default: fwd_batch_tile<4>(it, e.y, s_lds[wib], s_te, s_kw[wib], lane); break;
+    }
     wave_lds_sync();
   }
+  batch_finish(ctr);
 }
 
-hipError_t launch_fwd_batch(int L, int C1, const BatchItem *items, const int2 *tiles, int64_t n_tiles,
-                            unsigned int *head, int blocks, hipStream_t s) {
-#define DWTFRAG_CASE(LL, CC)                                                                    \
-  if (L == LL && C1 == CC) {                                                                    \
-    hipLaunchKernelGGL((fwd_batch_kernel<LL, CC>), dim3(blocks), dim3(kBlockThreads), 0, s,     \
-                       items, tiles, n_tiles, head);                                            \
-    return hipGetLastError();                                                                   \
-  }
-  DWTFRAG_CASE(1, 8) DWTFRAG_CASE(2, 8) DWTFRAG_CASE(3, 8)
-  DWTFRAG_CASE(1, 16) DWTFRAG_CASE(2, 16) DWTFRAG_CASE(3, 16) DWTFRAG_CASE(4, 16)
-#undef DWTFRAG_CASE
-  return hipErrorInvalidValue;
+hipError_t launch_fwd_batch(const BatchItem *items, const int2 *tiles, int64_t n_tiles,
+                            BatchCounters *ctr, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(fwd_batch_kernel, dim3(blocks), dim3(kBlockThreads), 0, s, items, tiles,
+                     n_tiles, ctr);
+  return hipGetLastError();
+}
+
+// Resident workgroups per CU of the batch forward kernel.
+int fwd_batch_blocks_per_cu() {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void *>(&fwd_batch_kernel),
+                                                   kBlockThreads, 0) != hipSuccess)
+    return 0;
+  return blocks;
 }
 
 // Resident wavefronts per CU of the forward kernel for (L, C1).

@@ -186,7 +186,7 @@ struct InvWave {
     Y0 = seg_start(P, seg);
     X1 = last_win ? P.W : X0 + P.own_w;
     Y1 = last_seg ? P.H : seg_start(P, seg + 1);
-    const int cbase = (win == 0) ? 0 : X0 - P.halo_l;
+    const int cbase = window_base(P, win);
     c0 = cbase + lane * C1;
     const int kbeg = (Y0 > P.halo_t ? Y0 - P.halo_t : 0) >> L;
     const int kend = min(P.hdim[L], (Y1 + P.halo_b) >> L);
@@ -507,7 +507,7 @@ struct InvWavePk {
     Y0 = seg_start(P, seg);
     X1 = last_win ? P.W : X0 + P.own_w;
     Y1 = last_seg ? P.H : seg_start(P, seg + 1);
-    const int cbase = (win == 0) ? 0 : X0 - P.halo_l;
+    const int cbase = window_base(P, win);
     c0 = cbase + lane * C1;
     const int kbeg = (Y0 > P.halo_t ? Y0 - P.halo_t : 0) >> L;
     const int kend = min(P.hdim[L], (Y1 + P.halo_b) >> L);
@@ -584,7 +584,7 @@ __device__ __forceinline__ void inv_setup(Wv &w, const int16_t *llin, const int1
 template <int L, int C1, bool U8OUT>
 __device__ __forceinline__ bool wave_is_fast(const StageParams &P, int wave, int lane) {
   const int win = wave % P.n_win;
-  const int cbase = (win == 0) ? 0 : win * P.own_w - P.halo_l;
+  const int cbase = window_base(P, win);
   const int c0 = cbase + lane * C1;
   bool bad = !U8OUT || P.W % C1 != 0 || c0 + C1 > P.W;
 #pragma unroll
@@ -655,6 +655,159 @@ void inv_kernel16(const int16_t *__restrict__ llin, const int16_t *__restrict__ 
   inv_body<L, 16, U8OUT>(llin, pub, out, P);
 }
 
+// ---- split restore -----------------------------------------------------
+// The 32-bit redo of a wavefront whose fragments hold values outside the
+// packed range is rare, but its code in the same kernel as the packed streams
+// costs those streams registers (spills).  For large byte outputs the restore
+// therefore runs as two launches: the packed kernel (no redo code) writes
+// kRedoMark into the first 16 bytes of a failed wavefront's output rectangle
+// after all of its stores; the redo kernel then reads those 16 bytes of every
+// rectangle and redoes, with the exact 32-bit stream, each one that holds the
+// mark.  A rectangle whose correct output happens to equal the mark is redone
+// too, which writes the same bytes: the mark decides only whether work is
+// repeated, never the result.
+__device__ __forceinline__ uint8_t redo_mark(int t) {
+  constexpr uint32_t kRedoMark[4] = {0x3C8E15A7u, 0xD24B96F1u, 0x0B7F63E9u, 0x95A1C40Du};
+  return uint8_t(kRedoMark[t >> 2] >> (8 * (t & 3)));
+}
+
+// Byte offset of a wavefront's output rectangle origin (its first owned row
+// and column).
+__device__ __forceinline__ int64_t rect_origin(const StageParams &P, int wave) {
+  const int win = wave % P.n_win;
+  const int seg = wave / P.n_win;
+  return int64_t(seg_start(P, seg)) * P.W + int64_t(win) * P.own_w;
+}
+
+// ALL_FAST: the host found every wavefront FAST (see inv_all_fast), so only
+// that stream is compiled in; a wavefront that is not (none, when the host is
+// right) marks its rectangle for the redo without streaming.
+template <int L, int C1, bool ALL_FAST>
+__device__ __forceinline__ void inv_split_pk_body(const int16_t *__restrict__ llin,
+                                                  const int16_t *__restrict__ pub,
+                                                  uint8_t *__restrict__ out, const StageParams &P) {
+  __shared__ uint32_t s_te[1024];
+  __shared__ uint32_t s_kw[kKeyWords];
+  __shared__ uint32_t s_ring[kWavesPerBlock][kRingBlocks * 4];
+  if (P.use_aes) load_aes_tables(s_te, s_kw, P.key);
+  __syncthreads();
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wave = blockIdx.x * kWavesPerBlock + wib;
+  if (wave >= P.n_waves) return;
+  const int lane = int(threadIdx.x & 63);
+  bool ok = false;
+  if (wave_is_fast<L, C1, true>(P, wave, lane)) {
+    InvWavePk<L, C1, true, true> w{P};
+    inv_setup(w, llin, pub, out, lane, s_ring[wib], s_te, s_kw);
+    ok = w.run(wave);
+  } else if constexpr (!ALL_FAST) {
+    InvWavePk<L, C1, true, false> w{P};
+    inv_setup(w, llin, pub, out, lane, s_ring[wib], s_te, s_kw);
+    ok = w.run(wave);
+  }
+  if (!ok) {
+    __threadfence();  // the wavefront's output stores land before the mark
+    if (lane < 16) glob(out)[rect_origin(P, wave) + lane] = redo_mark(lane);
+  }
+}
+
+template <int L, int C1>
+__device__ __forceinline__ void inv_split_redo_body(const int16_t *__restrict__ llin,
+                                                    const int16_t *__restrict__ pub,
+                                                    uint8_t *__restrict__ out, const StageParams &P) {
+  __shared__ uint32_t s_te[1024];
+  __shared__ uint32_t s_kw[kKeyWords];
+  __shared__ uint32_t s_ring[kWavesPerBlock][kRingBlocks * 4];
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wave = blockIdx.x * kWavesPerBlock + wib;
+  const int lane = int(threadIdx.x & 63);
+  bool marked = false;
+  if (wave < P.n_waves) {
+    const bool diff = lane < 16 && glob(out)[rect_origin(P, wave) + lane] != redo_mark(lane);
+    marked = __builtin_amdgcn_ballot_w64(diff) == 0;
+  }
+  // tables only for workgroups with a marked rectangle
+  const bool any = __syncthreads_or(marked) != 0;
+  if (!any) return;
+  if (P.use_aes) load_aes_tables(s_te, s_kw, P.key);
+  __syncthreads();
+  if (!marked) return;
+  InvWave<L, C1, true> x{P};
+  inv_setup(x, llin, pub, out, lane, s_ring[wib], s_te, s_kw);
+  x.run(wave);
+}
+
+template <int L, bool ALL_FAST>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void inv_split_pk8(const int16_t *__restrict__ llin, const int16_t *__restrict__ pub,
+                   uint8_t *__restrict__ out, const StageParams P) {
+  inv_split_pk_body<L, 8, ALL_FAST>(llin, pub, out, P);
+}
+template <int L, bool ALL_FAST>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void inv_split_pk16(const int16_t *__restrict__ llin, const int16_t *__restrict__ pub,
+                    uint8_t *__restrict__ out, const StageParams P) {
+  inv_split_pk_body<L, 16, ALL_FAST>(llin, pub, out, P);
+}
+template <int L, int C1>
+__global__ __launch_bounds__(kBlockThreads)
+void inv_split_redo(const int16_t *__restrict__ llin, const int16_t *__restrict__ pub,
+                    uint8_t *__restrict__ out, const StageParams P) {
+  inv_split_redo_body<L, C1>(llin, pub, out, P);
+}
+
+// Whether a byte-output stage runs as the split pair: large enough that the
+// second launch is negligible, and every rectangle's first row is complete
+// and holds at least 16 owned columns (room for the mark).
+static bool inv_split_ok(const StageParams &P) {
+  if (P.n_valid < (int64_t(1) << 24)) return false;
+  const int last_w = P.W - (P.n_win - 1) * P.own_w;
+  if ((P.n_win > 1 && P.own_w < 16) || last_w < 16) return false;
+  const int64_t last_y0 = int64_t(P.unit_rows) * ((int64_t(P.n_seg - 1) * P.units) / P.n_seg);
+  return (last_y0 + 1) * P.W <= P.n_valid;
+}
+
+// Host mirror of wave_is_fast over every window (the lane with the largest
+// column decides each window): whether all wavefronts of the stage are FAST.
+static bool inv_all_fast(const StageParams &P, int L, int C1) {
+  if (P.W % C1 != 0) return false;
+  for (int win = 0; win < P.n_win; ++win) {
+    const int cbase = win == 0 ? 0 : (win == P.n_win - 1 ? P.last_base : win * P.own_w - P.halo_l);
+    const int64_t c0 = int64_t(cbase) + 63 * C1;
+    if (c0 + C1 > P.W) return false;
+    for (int l = 1; l <= L; ++l) {
+      const int uu = (C1 >> (l - 1)) / 2;
+      const int64_t wl = P.wdim[l], wh = P.wdim[l - 1] - P.wdim[l], bc = c0 >> l;
+      if (wl % uu || wh % uu || P.off_hl[l] % uu || P.off_lh[l] % uu || P.off_hh[l] % uu ||
+          wl - bc < uu || wh - bc < uu)
+        return false;
+    }
+  }
+  return true;
+}
+
+template <int L, int C1>
+static hipError_t launch_inv_split(const int16_t *llin, const int16_t *pub, uint8_t *out,
+                                   const StageParams &P, hipStream_t s) {
+  const int blocks = (P.n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
+  const bool all_fast = inv_all_fast(P, L, C1);
+  if constexpr (C1 == 8) {
+    if (all_fast)
+      hipLaunchKernelGGL((inv_split_pk8<L, true>), dim3(blocks), dim3(kBlockThreads), 0, s, llin, pub, out, P);
+    else
+      hipLaunchKernelGGL((inv_split_pk8<L, false>), dim3(blocks), dim3(kBlockThreads), 0, s, llin, pub, out, P);
+  } else {
+    if (all_fast)
+      hipLaunchKernelGGL((inv_split_pk16<L, true>), dim3(blocks), dim3(kBlockThreads), 0, s, llin, pub, out, P);
+    else
+      hipLaunchKernelGGL((inv_split_pk16<L, false>), dim3(blocks), dim3(kBlockThreads), 0, s, llin, pub, out, P);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((inv_split_redo<L, C1>), dim3(blocks), dim3(kBlockThreads), 0, s, llin, pub, out, P);
+  return hipGetLastError();
+}
+
 template <int L, int C1, bool U8OUT>
 static const void *inv_fn() {
   if constexpr (C1 == 8) return reinterpret_cast<const void *>(&inv_kernel8<L, U8OUT>);
@@ -674,13 +827,13 @@ static hipError_t launch_inv_t(const int16_t *llin, const int16_t *pub, void *ou
   return hipGetLastError();
 }
 
-// Batch form: a persistent launch drains one class's tile queue.  Items carry
-// their own keys: each wavefront stages its tile's round keys and nonce in
-// its own LDS slot.
-template <int L, int C1>
-__device__ __forceinline__ void inv_batch_body(const BatchItem *__restrict__ items,
-                                               const int2 *__restrict__ tiles, int64_t n_tiles,
-                                               unsigned int *__restrict__ head) {
+// Batch form: one persistent launch drains the batch's tile queue.  Items
+// carry their own keys: each wavefront stages its tile's round keys and
+// nonce in its own LDS slot; a tile runs the inverse of its item's depth.
+// Sixteen columns per lane: two wavefronts per SIMD (256 VGPRs).
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void inv_batch_kernel(const BatchItem *__restrict__ items, const int2 *__restrict__ tiles,
+                      int64_t n_tiles, BatchCounters *__restrict__ ctr) {
   __shared__ uint32_t s_te[1024];
   __shared__ uint32_t s_kw[kWavesPerBlock][kKeyWords];
   __shared__ uint32_t s_ring[kWavesPerBlock][kRingBlocks * 4];
@@ -690,47 +843,39 @@ __device__ __forceinline__ void inv_batch_body(const BatchItem *__restrict__ ite
   const int lane = threadIdx.x & 63;
   for (;;) {
     unsigned int t = 0;
-    if (lane == 0) t = atomicAdd(head, 1u);
+    if (lane == 0) t = atomicAdd(&ctr->head, 1u);
     t = __builtin_amdgcn_readfirstlane(t);
     if (int64_t(t) >= n_tiles) break;
     const int2 e = tiles[t];
     const BatchItem &it = items[e.x];
     if (lane < kKeyWords) s_kw[wib][lane] = key_word(it.inv.key, lane);  // this item's keys
     wave_lds_sync();
-    inv_wave<L, C1, true>(it.inv, e.y, reinterpret_cast<const int16_t *>(it.priv), it.pub, it.out, lane,
-                          s_ring[wib], s_te, s_kw[wib]);
+    const int16_t *ll = reinterpret_cast<const int16_t *>(it.priv);
+    switch (__builtin_amdgcn_readfirstlane(it.levels)) {
+      case 1: inv_wave<1, kBatchCols, true>(it.inv, e.y, ll, it.pub, it.out, lane, s_ring[wib], s_te, s_kw[wib]); break;
+      case 2: inv_wave<2, kBatchCols, true>(it.inv, e.y, ll, it.pub, it.out, lane, s_ring[wib], s_te, s_kw[wib]); break;
+      case 3: inv_wave<3, kBatchCols, true>(it.inv, e.y, ll, it.pub, it.out, lane, s_ring[wib], s_te, s_kw[wib]); break;
+      default: inv_wave<4, kBatchCols, true>(it.inv, e.y, ll, it.pub, it.out, lane, s_ring[wib], s_te, s_kw[wib]); break;
+    }
     wave_lds_sync();
   }
+  batch_finish(ctr);
 }
 
-template <int L>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(4)))
-void inv_batch_kernel8(const BatchItem *__restrict__ items, const int2 *__restrict__ tiles,
-                       int64_t n_tiles, unsigned int *__restrict__ head) {
-  inv_batch_body<L, 8>(items, tiles, n_tiles, head);
+hipError_t launch_inv_batch(const BatchItem *items, const int2 *tiles, int64_t n_tiles,
+                            BatchCounters *ctr, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(inv_batch_kernel, dim3(blocks), dim3(kBlockThreads), 0, s, items, tiles,
+                     n_tiles, ctr);
+  return hipGetLastError();
 }
 
-template <int L>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2)))
-void inv_batch_kernel16(const BatchItem *__restrict__ items, const int2 *__restrict__ tiles,
-                        int64_t n_tiles, unsigned int *__restrict__ head) {
-  inv_batch_body<L, 16>(items, tiles, n_tiles, head);
-}
-
-hipError_t launch_inv_batch(int L, int C1, const BatchItem *items, const int2 *tiles, int64_t n_tiles,
-                            unsigned int *head, int blocks, hipStream_t s) {
-#define DWTFRAG_CASE(LL, CC, K)                                                              \
-  if (L == LL && C1 == CC) {                                                                 \
-    hipLaunchKernelGGL((K<LL>), dim3(blocks), dim3(kBlockThreads), 0, s, items, tiles,       \
-                       n_tiles, head);                                                       \
-    return hipGetLastError();                                                                \
-  }
-  DWTFRAG_CASE(1, 8, inv_batch_kernel8) DWTFRAG_CASE(2, 8, inv_batch_kernel8)
-  DWTFRAG_CASE(3, 8, inv_batch_kernel8) DWTFRAG_CASE(1, 16, inv_batch_kernel16)
-  DWTFRAG_CASE(2, 16, inv_batch_kernel16) DWTFRAG_CASE(3, 16, inv_batch_kernel16)
-  DWTFRAG_CASE(4, 16, inv_batch_kernel16)
-#undef DWTFRAG_CASE
-  return hipErrorInvalidValue;
+// Resident workgroups per CU of the batch inverse kernel.
+int inv_batch_blocks_per_cu() {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void *>(&inv_batch_kernel),
+                                                   kBlockThreads, 0) != hipSuccess)
+    return 0;
+  return blocks;
 }
 
 // Resident wavefronts per CU of the inverse kernel for (L, C1).
@@ -749,9 +894,11 @@ int inv_waves_per_cu(int L, int C1, bool u8out) {
 
 hipError_t launch_inv(int L, int C1, bool u8out, const int16_t *llin, const int16_t *pub,
                       void *out, const StageParams &P, hipStream_t s) {
+  const bool split = u8out && inv_split_ok(P);
 #define DWTFRAG_CASE(LL, CC)                                                   \
   if (L == LL && C1 == CC)                                                     \
-    return u8out ? launch_inv_t<LL, CC, true>(llin, pub, out, P, s)            \
+    return split ? launch_inv_split<LL, CC>(llin, pub, static_cast<uint8_t *>(out), P, s) \
+         : u8out ? launch_inv_t<LL, CC, true>(llin, pub, out, P, s)            \
                  : launch_inv_t<LL, CC, false>(llin, pub, out, P, s);
   DWTFRAG_CASE(1, 8) DWTFRAG_CASE(2, 8) DWTFRAG_CASE(3, 8)
   DWTFRAG_CASE(1, 16) DWTFRAG_CASE(2, 16) DWTFRAG_CASE(3, 16) DWTFRAG_CASE(4, 16)

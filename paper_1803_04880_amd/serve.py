@@ -13,6 +13,8 @@ computes each item independently).
 
 The per-request latency is arrival -> completion as seen by the host (the
 event's completion is polled; the clock is ``time.perf_counter``).
+``warmup()`` runs the batch kernels once on both streams before arrivals
+start; ``launch_log`` keeps each launch's host launch and retire times.
 """
 from __future__ import annotations
 
@@ -56,6 +58,7 @@ class _InFlight:
     event: torch.cuda.Event
     bytes: int
     batches: list
+    launched: float = 0.0        # host clock at launch (seconds from the run's start)
 
 
 class Server:
@@ -73,6 +76,28 @@ class Server:
         self.inflight: deque[_InFlight] = deque()
         self.batches_launched = 0
         self.on_complete = None   # called with each request when its batch has finished
+        # per launch: (launch time, retire time, requests, bytes), host clock
+        self.launch_log: list[tuple[float, float, int, int]] = []
+        self._now = time.perf_counter
+
+    def warmup(self):
+        """Run one small protect + restore batch of every depth on each stream
+        and wait for it, so that the first launches of the batch kernels, the
+        streams' first events and the first plan uploads happen before any
+        request arrives."""
+        key = bytes(16)
+        for st in self.streams:
+            with torch.cuda.stream(st):
+                xs = [torch.full((4096 * lv + 17,), lv, dtype=torch.uint8, device=self.device)
+                      for lv in (1, 2, 3, 4)]
+                ws = [64] * 4
+                b = Batch(xs, ws, [1, 2, 3, 4], [key] * 4, [key] * 4)
+                b.protect(stream=st)
+                b.restore(stream=st)
+                ev = torch.cuda.Event()
+                ev.record(st)
+            ev.synchronize()
+            b.close()
 
     def _launch(self, reqs):
         prot = [r for r in reqs if r.op == "protect"]
@@ -110,7 +135,7 @@ class Server:
             ev = torch.cuda.Event()
             ev.record(stream)
         self.in_use += used
-        self.inflight.append(_InFlight(reqs, ev, used, batches))
+        self.inflight.append(_InFlight(reqs, ev, used, batches, self._now()))
         self.batches_launched += 1
 
     def _retire(self, now_fn, block=False):
@@ -121,6 +146,7 @@ class Server:
             elif not f.event.query():
                 return
             t = now_fn()
+            self.launch_log.append((f.launched, t, len(f.reqs), f.bytes))
             for r in f.reqs:
                 r.done = t
                 if self.on_complete is not None:
@@ -136,6 +162,7 @@ class Server:
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0  # noqa: E731
+        self._now = now
         waiting: deque[Request] = deque()
         while pending or waiting or self.inflight:
             t = now()

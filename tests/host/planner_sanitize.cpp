@@ -19,12 +19,14 @@ hipError_t launch_inv(int, int, bool, const int16_t *, const int16_t *, void *,
                       const StageParams &, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_ctr(const uint8_t *, uint8_t *, uint64_t, const AesKey &, uint64_t,
                       hipStream_t) { return hipErrorInvalidValue; }
-hipError_t launch_fwd_batch(int, int, const BatchItem *, const int2 *, int64_t, unsigned int *, int,
+hipError_t launch_fwd_batch(const BatchItem *, const int2 *, int64_t, BatchCounters *, int,
                             hipStream_t) { return hipErrorInvalidValue; }
-hipError_t launch_inv_batch(int, int, const BatchItem *, const int2 *, int64_t, unsigned int *, int,
+hipError_t launch_inv_batch(const BatchItem *, const int2 *, int64_t, BatchCounters *, int,
                             hipStream_t) { return hipErrorInvalidValue; }
 int fwd_waves_per_cu(int L, int C1, bool) { return C1 == 16 ? 8 : 12 + L % 2; }
 int inv_waves_per_cu(int L, int C1, bool) { return C1 == 16 ? 8 : 16 - L % 2; }
+int fwd_batch_blocks_per_cu() { return 2; }
+int inv_batch_blocks_per_cu() { return 2; }
 }  // namespace dwtfrag
 
 static int failures = 0;
@@ -97,6 +99,7 @@ int main() {
   EXPECT(dwtfrag_batch_create(items.data(), uint32_t(items.size()), tune, 3, &b) == DWTFRAG_OK);
   EXPECT(b && dwtfrag_batch_device_bytes(b) > 0);
   EXPECT(dwtfrag_batch_protect(b, nullptr) == DWTFRAG_EINVAL);  // not uploaded
+  EXPECT(dwtfrag_batch_restore(b, nullptr) == DWTFRAG_EINVAL);
   dwtfrag_batch_destroy(b);
   items[3].levels = 5;
   EXPECT(dwtfrag_batch_create(items.data(), uint32_t(items.size()), nullptr, 0, &b) == DWTFRAG_EINVAL);

@@ -152,6 +152,33 @@ def test_restore_with_one_value_outside_packed_range(levels, where, value):
     assert got == fragment.restore(priv, pubb, n, width, levels, key, nonce)
 
 
+@pytest.mark.parametrize("levels", [1, 2, 3, 4])
+def test_large_restore_with_values_outside_packed_range(levels):
+    """A restore large enough for the two-launch form (packed streams, then
+    the 32-bit redo of the rectangles they mark): fragments of real data with
+    values moved outside the packed range in the private band, in the first
+    and last columns of detail rows and at random places; every byte must
+    equal the exact inverse."""
+    n, width = (1 << 24) + 12345, 4096
+    rng = np.random.default_rng(400 + levels)
+    buf = rng.integers(0, 256, n, dtype=np.uint8)
+    key, nonce = rng.bytes(16), rng.bytes(16)
+    opriv, opub = fragment.protect(buf, width, levels, key, nonce)
+    ll = np.frombuffer(aes128.ctr_xor(key, nonce, opriv).tobytes(), "<i2").copy()
+    pub = np.frombuffer(opub, "<i2").copy()
+    g = fragment.geometry(n, width, levels)
+    wl = g["shapes"][1][1]          # level-1 LL width = HL row stride start
+    ll[int(rng.integers(0, ll.size))] = -30000
+    pub[-1] = 5000                   # last coefficient (bottom-right HH)
+    pub[pub.size - wl] = -5000       # start of the last HH row
+    for idx in rng.integers(0, pub.size, 5):
+        pub[int(idx)] = int(rng.choice([-32768, 32767, 4096, -4097]))
+    priv, pubb = _fragments_from_values(ll, pub, key, nonce)
+    _say(f"large restore with values outside: levels={levels}")
+    got = _gpu_restore(priv, pubb, n, width, levels, key, nonce)
+    assert got == fragment.restore(priv, pubb, n, width, levels, key, nonce)
+
+
 @pytest.mark.parametrize("levels", [2, 3])
 def test_restore_of_small_arbitrary_fragments(levels):
     """Arbitrary coefficients in [-600, 600] (LL included): packed where the
