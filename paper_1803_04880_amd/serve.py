@@ -80,11 +80,18 @@ class Server:
         self.launch_log: list[tuple[float, float, int, int]] = []
         self._now = time.perf_counter
 
-    def warmup(self):
+    def warmup(self, reserve_bytes: int = 4 << 30):
         """Run one small protect + restore batch of every depth on each stream
         and wait for it, so that the first launches of the batch kernels, the
         streams' first events and the first plan uploads happen before any
-        request arrives."""
+        request arrives; then allocate and free ``reserve_bytes`` on each
+        stream so that torch's caching allocator holds that much device
+        memory for the results of the first launches (a first-time device
+        allocation of tens of MB stalls the host for milliseconds)."""
+        for st in self.streams:
+            with torch.cuda.stream(st):
+                block = torch.empty(reserve_bytes, dtype=torch.uint8, device=self.device)
+                del block
         key = bytes(16)
         for st in self.streams:
             with torch.cuda.stream(st):
