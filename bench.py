@@ -269,6 +269,8 @@ def main():
     ap.add_argument("--seg-rows", type=int, default=0)
     ap.add_argument("--lane-cols", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-small", action="store_true",
+                    help="large config: skip the 512 x 512 latency measurement")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--profile-run", action="store_true",
                     help="no timing: 2 plain device copies of n bytes and 2 of n/4 bytes "
@@ -464,10 +466,57 @@ def main():
         "device_copy": device_copy,
         "cpu_baseline": None,
     }
+    if args.config == "large" and not args.no_small:
+        result["small_latency_us"] = small_latency(dev, stream)
     if not args.no_cpu_baseline and args.config == "large":
         log("timing the CPU oracle on a bounded sample ...")
         result["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(result), flush=True)
+
+
+def small_latency(dev, stream, steps: int = 1000, warmup: int = 50):
+    """Latency of the 512 x 512, one-level workload (inputs resident, warm):
+    p50 / p99 of protect, restore and the pair from HIP events, after a
+    byte-for-byte check against the oracle's stored digests."""
+    import torch
+
+    import paper_1803_04880_amd as dwtfrag
+    import synth
+    cfg = synth.config_small()
+    buf = cfg["buf"]
+    n, w, lv, key, nonce = buf.size, cfg["width"], cfg["levels"], cfg["key"], cfg["nonce"]
+    g = dwtfrag.geometry(n, w, lv)
+    x = torch.from_numpy(buf).to(dev)
+    priv = torch.empty(g["priv_bytes"], dtype=torch.uint8, device=dev)
+    pub = torch.empty(g["pub_bytes"] // 2, dtype=torch.int16, device=dev)
+    out = torch.empty(n, dtype=torch.uint8, device=dev)
+    dwtfrag.protect(x, w, lv, key, nonce, priv=priv, pub=pub)
+    dwtfrag.restore(priv, pub, n, w, lv, key, nonce, out=out)
+    torch.cuda.synchronize()
+    with open(os.path.join(ROOT, "tests", "golden", "oracle_digests.json")) as f:
+        gold = json.load(f)["small"]
+    exact = (hashlib.sha256(priv.cpu().numpy().tobytes()).hexdigest() == gold["priv_sha256"]
+             and hashlib.sha256(pub.cpu().numpy().tobytes()).hexdigest() == gold["pub_sha256"]
+             and bool(torch.equal(out, x)))
+    for _ in range(warmup):
+        dwtfrag.protect(x, w, lv, key, nonce, priv=priv, pub=pub)
+        dwtfrag.restore(priv, pub, n, w, lv, key, nonce, out=out)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        dwtfrag.protect(x, w, lv, key, nonce, priv=priv, pub=pub)
+        ev[k][1].record(stream)
+        dwtfrag.restore(priv, pub, n, w, lv, key, nonce, out=out)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    tp = [ev[k][0].elapsed_time(ev[k][1]) * 1e3 for k in range(steps)]
+    tr = [ev[k][1].elapsed_time(ev[k][2]) * 1e3 for k in range(steps)]
+    tq = [a + b for a, b in zip(tp, tr)]
+    return {"workload": cfg["name"], "steps": steps, "bit_exact": exact,
+            "protect_p50": round(percentile(tp, 50), 1), "protect_p99": round(percentile(tp, 99), 1),
+            "restore_p50": round(percentile(tr, 50), 1), "restore_p99": round(percentile(tr, 99), 1),
+            "pair_p50": round(percentile(tq, 50), 1), "pair_p99": round(percentile(tq, 99), 1)}
 
 
 # Algorithmic VALU instructions per 8x8 block of the blocked protection: the
@@ -715,14 +764,20 @@ def run_batch(args):
 
 def _launch_stats(log):
     """p50 / p99 / max of launch -> retire (host clock) over the server's
-    launches, with the requests and bytes of the slowest."""
+    launches; for the slowest: its planning time, its kernels' device time,
+    requests and bytes."""
     if not log:
         return None
-    d = [(r - l) * 1e3 for l, r, _, _ in log]
+    d = [(r - l) * 1e3 for _, l, r, _, _, _ in log]
+    g = [gm for _, _, _, gm, _, _ in log]
     worst = max(range(len(log)), key=lambda i: d[i])
+    p0, l0, _, gm, nreq, nb = log[worst]
     return {"p50": round(percentile(d, 50), 3), "p99": round(percentile(d, 99), 3),
-            "max": round(d[worst], 3), "max_at_s": round(log[worst][0], 3),
-            "max_requests": log[worst][2], "max_bytes": log[worst][3]}
+            "max": round(d[worst], 3), "max_at_s": round(l0, 3),
+            "max_planning_ms": round((l0 - p0) * 1e3, 3), "max_device_ms": round(gm, 3),
+            "max_requests": nreq, "max_bytes": nb,
+            "device_ms_p50": round(percentile(g, 50), 3), "device_ms_max": round(max(g), 3),
+            "planning_ms_max": round(max((l - p) * 1e3 for p, l, _, _, _, _ in log), 3)}
 
 
 def run_serve(args):
@@ -802,6 +857,7 @@ def run_serve(args):
                        "max": round(max(lat), 3)},
         "launches": srv.batches_launched, "wall_s": round(wall, 3),
         "launch_to_retire_ms": _launch_stats(srv.launch_log),
+        "host_loop_max_ms": round(srv.max_gap[0] * 1e3, 3), "host_loop_max_at_s": round(srv.max_gap[1], 3),
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(result), flush=True)

@@ -15,6 +15,10 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdwtfrag.so")
 SOURCES = ["api.hip", "batch.hip", "fwd.hip", "inv.hip", "ctr.hip", "learned.hip", "se8.hip"]
 ARCH = os.environ.get("DWTFRAG_ARCH", "gfx950")
+# Per-source compiler options: the SHA-2 compressions of se8.hip are fully
+# unrolled loops (their message schedule lives in registers only when every
+# index is a constant), larger than the unroller's default size limit.
+EXTRA = {"se8.hip": ["-mllvm", "-pragma-unroll-threshold=500000"]}
 
 
 def hipcc() -> str:
@@ -37,7 +41,7 @@ def build(verbose: bool = False) -> str:
     objs, procs = [], []
     for src in SOURCES:  # independent translation units: compile in parallel
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [hipcc()] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc()] + flags() + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd), src))

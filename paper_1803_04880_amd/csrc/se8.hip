@@ -144,9 +144,47 @@ __device__ __forceinline__ int get_bits(const uint32_t (&w)[kWords], int pos, in
 }
 
 // ---------------------------------------------------------------- SHA-2 ----
-// FIPS 180-4 compressions of one padded message block.
-__device__ __forceinline__ uint32_t rotr32(uint32_t x, int n) { return (x >> n) | (x << (32 - n)); }
-__device__ __forceinline__ uint64_t rotr64(uint64_t x, int n) { return (x >> n) | (x << (64 - n)); }
+// FIPS 180-4 compressions of one padded message block.  Every logical
+// function maps onto single gfx950 instructions: a 32-bit rotate is one
+// funnel shift (v_alignbit), a 64-bit rotate or shift two (one per half), a
+// three-way XOR, choose or majority one three-input bit operation per 32
+// bits (v_bitop3 truth tables 0x96, 0xCA, 0xE8), and 64-bit additions stay
+// 64-bit operations.
+__device__ __forceinline__ uint32_t rotr32(uint32_t x, int n) {
+  return __builtin_amdgcn_alignbit(x, x, n);
+}
+__device__ __forceinline__ uint32_t ch32(uint32_t e, uint32_t f, uint32_t g) {
+  return __builtin_amdgcn_bitop3_b32(e, f, g, 0xCA);  // e ? f : g
+}
+__device__ __forceinline__ uint32_t maj32(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);  // majority
+}
+
+__device__ __forceinline__ uint32_t lo32(uint64_t x) { return uint32_t(x); }
+__device__ __forceinline__ uint32_t hi32(uint64_t x) { return uint32_t(x >> 32); }
+__device__ __forceinline__ uint64_t join(uint32_t hi, uint32_t lo) { return (uint64_t(hi) << 32) | lo; }
+
+// rotate right by a constant 0 < N < 64: bits of the two halves funnel
+// through each other
+template <int N> __device__ __forceinline__ uint64_t rotr64(uint64_t x) {
+  const uint32_t lo = N >= 32 ? hi32(x) : lo32(x), hi = N >= 32 ? lo32(x) : hi32(x);
+  constexpr int n = N % 32;
+  if constexpr (n == 0) return join(hi, lo);
+  else return join(__builtin_amdgcn_alignbit(lo, hi, n), __builtin_amdgcn_alignbit(hi, lo, n));
+}
+// logical shift right by a constant 0 < N < 32
+template <int N> __device__ __forceinline__ uint64_t shr64(uint64_t x) {
+  return join(hi32(x) >> N, __builtin_amdgcn_alignbit(hi32(x), lo32(x), N));
+}
+__device__ __forceinline__ uint64_t xor3_64(uint64_t a, uint64_t b, uint64_t c) {
+  return join(xor3(hi32(a), hi32(b), hi32(c)), xor3(lo32(a), lo32(b), lo32(c)));
+}
+__device__ __forceinline__ uint64_t ch64(uint64_t e, uint64_t f, uint64_t g) {
+  return join(ch32(hi32(e), hi32(f), hi32(g)), ch32(lo32(e), lo32(f), lo32(g)));
+}
+__device__ __forceinline__ uint64_t maj64(uint64_t a, uint64_t b, uint64_t c) {
+  return join(maj32(hi32(a), hi32(b), hi32(c)), maj32(lo32(a), lo32(b), lo32(c)));
+}
 
 __device__ __forceinline__ void sha256_block(const Sha2Tables &T, uint32_t (&W)[16], uint32_t (&H)[8]) {
   uint32_t a = T.h256[0], b = T.h256[1], c = T.h256[2], d = T.h256[3];
@@ -158,15 +196,14 @@ __device__ __forceinline__ void sha256_block(const Sha2Tables &T, uint32_t (&W)[
       wt = W[t];
     } else {
       const uint32_t w15 = W[(t - 15) & 15], w2 = W[(t - 2) & 15];
-      const uint32_t s0 = rotr32(w15, 7) ^ rotr32(w15, 18) ^ (w15 >> 3);
-      const uint32_t s1 = rotr32(w2, 17) ^ rotr32(w2, 19) ^ (w2 >> 10);
+      const uint32_t s0 = xor3(rotr32(w15, 7), rotr32(w15, 18), w15 >> 3);
+      const uint32_t s1 = xor3(rotr32(w2, 17), rotr32(w2, 19), w2 >> 10);
       wt = W[t & 15] = W[t & 15] + s0 + W[(t - 7) & 15] + s1;
     }
-    const uint32_t S1 = rotr32(e, 6) ^ rotr32(e, 11) ^ rotr32(e, 25);
-    const uint32_t ch = (e & f) ^ (~e & g);
-    const uint32_t t1 = h + S1 + ch + T.k256[t] + wt;
-    const uint32_t S0 = rotr32(a, 2) ^ rotr32(a, 13) ^ rotr32(a, 22);
-    const uint32_t mj = (a & b) ^ (a & c) ^ (b & c);
+    const uint32_t S1 = xor3(rotr32(e, 6), rotr32(e, 11), rotr32(e, 25));
+    const uint32_t t1 = h + S1 + ch32(e, f, g) + T.k256[t] + wt;
+    const uint32_t S0 = xor3(rotr32(a, 2), rotr32(a, 13), rotr32(a, 22));
+    const uint32_t mj = maj32(a, b, c);
     h = g; g = f; f = e; e = d + t1;
     d = c; c = b; b = a; a = t1 + S0 + mj;
   }
@@ -184,15 +221,14 @@ __device__ __forceinline__ void sha512_block(const Sha2Tables &T, uint64_t (&W)[
       wt = W[t];
     } else {
       const uint64_t w15 = W[(t - 15) & 15], w2 = W[(t - 2) & 15];
-      const uint64_t s0 = rotr64(w15, 1) ^ rotr64(w15, 8) ^ (w15 >> 7);
-      const uint64_t s1 = rotr64(w2, 19) ^ rotr64(w2, 61) ^ (w2 >> 6);
+      const uint64_t s0 = xor3_64(rotr64<1>(w15), rotr64<8>(w15), shr64<7>(w15));
+      const uint64_t s1 = xor3_64(rotr64<19>(w2), rotr64<61>(w2), shr64<6>(w2));
       wt = W[t & 15] = W[t & 15] + s0 + W[(t - 7) & 15] + s1;
     }
-    const uint64_t S1 = rotr64(e, 14) ^ rotr64(e, 18) ^ rotr64(e, 41);
-    const uint64_t ch = (e & f) ^ (~e & g);
-    const uint64_t t1 = h + S1 + ch + T.k512[t] + wt;
-    const uint64_t S0 = rotr64(a, 28) ^ rotr64(a, 34) ^ rotr64(a, 39);
-    const uint64_t mj = (a & b) ^ (a & c) ^ (b & c);
+    const uint64_t S1 = xor3_64(rotr64<14>(e), rotr64<18>(e), rotr64<41>(e));
+    const uint64_t t1 = h + S1 + ch64(e, f, g) + T.k512[t] + wt;
+    const uint64_t S0 = xor3_64(rotr64<28>(a), rotr64<34>(a), rotr64<39>(a));
+    const uint64_t mj = maj64(a, b, c);
     h = g; g = f; f = e; e = d + t1;
     d = c; c = b; b = a; a = t1 + S0 + mj;
   }
