@@ -242,8 +242,21 @@ def cpu_baseline(cfg, rows: int = 2048, row0: int = 2048):
         dtp = time.perf_counter() - t0
     _SH.clear()
     assert (ppriv, ppub, pback) == (priv, pub, sample.tobytes()), "pooled oracle differs"
+    # the 512 x 512, one-level workload whole, one process (a fraction of a second)
+    import synth
+    small = synth.config_small()
+    t0 = time.perf_counter()
+    spriv, spub = fragment.protect(small["buf"], small["width"], small["levels"], small["key"],
+                                   small["nonce"])
+    sback = fragment.restore(spriv, spub, small["buf"].size, small["width"], small["levels"],
+                             small["key"], small["nonce"])
+    dts = time.perf_counter() - t0
+    assert sback == small["buf"].tobytes()
     return dict(value=round(sample.size / dtp / 1e9, 4), unit="GB/s", cores=cores, kind="oracle",
                 cpu_model=_cpu_model(),
+                small_workload=dict(value=round(small["buf"].size / dts / 1e9, 5),
+                                    seconds=round(dts, 4), workload=small["name"],
+                                    processes=1),
                 one_process=dict(value=round(sample.size / dt1 / 1e9, 4), seconds=round(dt1, 2)),
                 openssl_aes128_ctr=_openssl_ctr(cores),
                 sample=f"rows {row0}..{row0 + rows} of the {w}-wide workload "
