@@ -836,23 +836,29 @@ def run_serve(args):
                                   priv=p if op == "restore" else None,
                                   pub=q if op == "restore" else None))
     srv = serve.Server(budget_bytes=64 << 30, max_batch=512)
-    # results are checked (a sample, against the lone calls that made the
-    # pool) and released as requests complete
+    # results are released as requests complete, except a sample that is
+    # kept and checked after the run against the lone calls that made the
+    # pool (a check inside the loop would synchronise the device under it)
     stride = max(1, len(reqs) // 50)
-    checks = []
+    kept = []
 
     def on_complete(r):
         if r.rid % stride == 0:
-            e = next(e for e in pool if e[3] == r.key and e[4] == r.nonce)
-            if r.op == "protect":
-                checks.append(bool(torch.equal(r.out_priv, e[6]) and torch.equal(r.out_pub, e[7])))
-            else:
-                checks.append(bool(torch.equal(r.out, e[5])))
+            kept.append((r, r.out_priv, r.out_pub, r.out))
         r.out_priv = r.out_pub = r.out = None
 
     srv.on_complete = on_complete
     srv.warmup()
     wall = srv.run(reqs)
+    torch.cuda.synchronize()
+    checks = []
+    for r, p, q, o in kept:
+        e = next(e for e in pool if e[3] == r.key and e[4] == r.nonce)
+        if r.op == "protect":
+            checks.append(bool(torch.equal(p, e[6]) and torch.equal(q, e[7])))
+        else:
+            checks.append(bool(torch.equal(o, e[5])))
+    del kept
     lat = [(r.done - r.arrival) * 1e3 for r in reqs]
     total = sum(r.n for r in reqs)
     ok = bool(checks) and all(checks)
