@@ -27,7 +27,7 @@ from collections import deque
 
 import torch
 
-from . import geometry
+from . import default_width, geometry
 from .batch import Batch
 
 
@@ -90,12 +90,13 @@ class Server:
         self.launch_log: list[tuple[float, float, float, float, int, int]] = []
         self._now = time.perf_counter
 
-    def warmup(self, reserve_bytes: int = 4 << 30):
-        """Run one small protect + restore batch of every depth on each stream
-        and wait for it, so that the first launches of the batch kernels, the
-        streams' first events and the first plan uploads happen before any
-        request arrives; allocate and free ``reserve_bytes`` on each stream so
-        that torch's caching allocator holds that much device memory for the
+    def warmup(self, reserve_bytes: int = 4 << 30, large_bytes: int = 256 << 20):
+        """Run one protect + restore batch on each stream and wait for it: a
+        small buffer of every depth and one of ``large_bytes``, so that the
+        first launches of the batch kernels, the streams' first timing events
+        and the first plan uploads, small and large, happen before any request
+        arrives; allocate and free ``reserve_bytes`` on each stream so that
+        torch's caching allocator holds that much device memory for the
         results of the first launches."""
         for st in self.streams:
             with torch.cuda.stream(st):
@@ -107,12 +108,20 @@ class Server:
                 xs = [torch.full((4096 * lv + 17,), lv, dtype=torch.uint8, device=self.device)
                       for lv in (1, 2, 3, 4)]
                 ws = [64] * 4
-                b = Batch(xs, ws, [1, 2, 3, 4], [key] * 4, [key] * 4)
+                lvs = [1, 2, 3, 4]
+                if large_bytes:
+                    xs.append(torch.zeros(large_bytes, dtype=torch.uint8, device=self.device))
+                    ws.append(default_width(large_bytes))
+                    lvs.append(3)
+                b = Batch(xs, ws, lvs, [key] * len(xs), [key] * len(xs))
+                start = torch.cuda.Event(enable_timing=True)
+                start.record(st)
                 b.protect(stream=st)
                 b.restore(stream=st)
-                ev = torch.cuda.Event()
+                ev = torch.cuda.Event(enable_timing=True)
                 ev.record(st)
             ev.synchronize()
+            start.elapsed_time(ev)   # the first timing query, off the request path
             b.close()
 
     def _launch(self, reqs):
