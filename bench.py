@@ -895,7 +895,8 @@ def run_learned(args):
     levels.  Trains the network on the GPU, then times learned and plain
     protect + restore over all images with the oracle-trained network of
     tests/golden (a fixed input, so the fragments can be checked against the
-    oracle's digest)."""
+    oracle's digest).  Learned calls are one per image, spread over four
+    streams; the plain path runs as one batch."""
     import multiprocessing
 
     import torch
@@ -924,15 +925,35 @@ def run_learned(args):
     privs = [torch.empty(g["priv_bytes"], dtype=torch.uint8, device=dev) for _ in range(nimg)]
     pubs = [torch.empty(g["pub_bytes"] // 2, dtype=torch.int16, device=dev) for _ in range(nimg)]
     outs = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(nimg)]
-    ws = GL.workspace(n, W, L, dev)
+    # The images are independent calls: they go round-robin to four streams
+    # (default priority), each with its own workspace, forked from and
+    # joined back into the current stream, so that one image's small levels
+    # overlap another's large one.  Image i's restore runs on the stream of
+    # its protect.
+    main = torch.cuda.current_stream()
+    n_streams = 4
+    side = [torch.cuda.Stream(device=dev) for _ in range(n_streams)]
+    wss = [GL.workspace(n, W, L, dev) for _ in range(n_streams)]
+
+    def fan_out(call):
+        fork = torch.cuda.Event()
+        fork.record(main)
+        for st in side:
+            st.wait_event(fork)
+        for i in range(nimg):
+            call(i, side[i % n_streams], wss[i % n_streams])
+        for st in side:
+            join = torch.cuda.Event()
+            join.record(st)
+            main.wait_event(join)
 
     def protect_all(net):
-        for i in range(nimg):
-            GL.protect(xs[i], W, L, kn[i][0], kn[i][1], net, priv=privs[i], pub=pubs[i], ws=ws)
+        fan_out(lambda i, st, ws: GL.protect(xs[i], W, L, kn[i][0], kn[i][1], net, priv=privs[i],
+                                             pub=pubs[i], ws=ws, stream=st))
 
     def restore_all(net):
-        for i in range(nimg):
-            GL.restore(privs[i], pubs[i], n, W, L, kn[i][0], kn[i][1], net, out=outs[i], ws=ws)
+        fan_out(lambda i, st, ws: GL.restore(privs[i], pubs[i], n, W, L, kn[i][0], kn[i][1], net,
+                                             out=outs[i], ws=ws, stream=st))
 
     from paper_1803_04880_amd import batch as B
     plain = B.Batch(xs, [W] * nimg, [L] * nimg, [k for k, _ in kn], [v for _, v in kn],

@@ -17,8 +17,12 @@ SOURCES = ["api.hip", "batch.hip", "fwd.hip", "inv.hip", "ctr.hip", "learned.hip
 ARCH = os.environ.get("DWTFRAG_ARCH", "gfx950")
 # Per-source compiler options: the SHA-2 compressions of se8.hip are fully
 # unrolled loops (their message schedule lives in registers only when every
-# index is a constant), larger than the unroller's default size limit.
-EXTRA = {"se8.hip": ["-mllvm", "-pragma-unroll-threshold=500000"]}
+# index is a constant), larger than the unroller's default size limit; the
+# matrix-core products of learned.hip write ordinary VGPRs, so that their
+# results need no copy out of the accumulator registers and the four
+# products of a batch can be in flight together.
+EXTRA = {"se8.hip": ["-mllvm", "-pragma-unroll-threshold=500000"],
+         "learned.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def hipcc() -> str:

@@ -15,13 +15,15 @@
 // Layout of the work: the network's hidden layer runs on the matrix cores
 // (int8 MFMA, see correction_mfma), its output layer and the context on the
 // VALU; that is still ~60 operations per predicted sample against ~2 for the
-// plain predict, so this path is ALU-bound and each 1-D pass runs as its own
-// kernel over int32 intermediates in HBM.  A block
-// takes SEG positions of LINES independent lines (rows: 1 line of 2048
-// positions; columns: 64 lines of 64 positions), loads them with an 8-sample
-// halo on each side, mirrored at the signal edges, into LDS as separate even
-// and odd planes (line index fastest, so lanes hit consecutive banks), then
-// predicts the odd samples and updates the even ones.
+// plain predict, so this path is ALU-bound.  Protect and restore run one
+// fused kernel per level and direction (both 1-D passes of a 64 x 128 tile
+// in LDS, int16 samples, halos recomputed), so the only HBM traffic is each
+// level's input and output.  The training-pair capture keeps one kernel per
+// 1-D pass: a block takes SEG positions of LINES independent lines (rows: 1
+// line of 2048 positions; columns: 64 lines of 64 positions), loads them with
+// an 8-sample halo on each side, mirrored at the signal edges, into LDS as
+// separate even and odd planes, then predicts the odd samples and updates
+// the even ones.
 //
 // The trainer fits the network with quantisation-aware Adam.  Its gradient
 // is taken at the fake-quantised parameters (integers over powers of two),
@@ -121,33 +123,37 @@ __device__ __forceinline__ MfmaNet mfma_net(const uint32_t *s_net, int b2, int s
   return m;
 }
 
-__device__ __forceinline__ int correction_mfma(const MfmaNet &m, const int (&e)[kCtx], int base,
-                                               int lane) {
+__device__ __forceinline__ int correction_mfma(const MfmaNet &m, const int (&e)[kCtx], int base) {
   int c[kCtx];
 #pragma unroll
   for (int j = 0; j < kCtx; ++j) c[j] = clamp_i(e[j] - base, -128, 127);
   const long b = long(pack4(c[0], c[1], c[2], c[3])) | (long(pack4(c[4], c[5], c[6], c[7])) << 32);
   // p[g]: this lane's quarter of the output sum of group g's sample l % 16
-  // (its four hidden units 4q..4q+3, q = l / 16)
+  // (its four hidden units 4q..4q+3, q = l / 16); the four products are
+  // independent, so they are all issued before the first result is read
+  v4i d[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) d[g] = __builtin_amdgcn_mfma_i32_16x16x32_i8(m.a[g], b, m.bias, 0, 0, 0);
   int p[4];
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
-    const v4i d = __builtin_amdgcn_mfma_i32_16x16x32_i8(m.a[g], b, m.bias, 0, 0, 0);
     int sum = 0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) sum += clamp_i(d[r], 0, 0x7fffff) * m.w2[r];
+    for (int r = 0; r < 4; ++r) sum += clamp_i(d[g][r], 0, 0x7fffff) * m.w2[r];
     p[g] = sum;
   }
   // Lane l needs group q's total: the sum of p[q] over lanes s, s+16, s+32,
-  // s+48 (s = l % 16).  Two exchange rounds: across lane halves (q ^ 2) each
-  // lane keeps the pair of groups {2(q/2), 2(q/2)+1} and sends the other
-  // pair; then across q ^ 1 it keeps group q and sends the other.
-  const int q = lane >> 4;
-  const bool hi = (q & 2) != 0;
-  const int k0 = (hi ? p[2] : p[0]) + __shfl_xor(hi ? p[0] : p[2], 32);
-  const int k1 = (hi ? p[3] : p[1]) + __shfl_xor(hi ? p[1] : p[3], 32);
-  const bool odd = (q & 1) != 0;
-  const int mine = (odd ? k1 : k0) + __shfl_xor(odd ? k0 : k1, 16);
+  // s+48 (s = l % 16, q = l / 16).  Swapping the upper 32 lanes of p[0]
+  // (p[1]) with the lower 32 lanes of p[2] (p[3]) leaves each lane both
+  // halves' terms of group 0 (1) in the lower half and of group 2 (3) in the
+  // upper half: k0 (k1) sums quarters {q, q ^ 2}.  Swapping the odd 16-lane
+  // rows of k0 with the even rows of k1 then gives every row r the two
+  // partial sums of group r.
+  const auto s02 = __builtin_amdgcn_permlane32_swap(unsigned(p[0]), unsigned(p[2]), false, false);
+  const auto s13 = __builtin_amdgcn_permlane32_swap(unsigned(p[1]), unsigned(p[3]), false, false);
+  const unsigned k0 = s02[0] + s02[1], k1 = s13[0] + s13[1];
+  const auto s01 = __builtin_amdgcn_permlane16_swap(k0, k1, false, false);
+  const int mine = int(s01[0] + s01[1]);
   return clamp_i((mine + m.b2) >> m.shift, -255, 255);
 }
 
@@ -225,47 +231,6 @@ struct Bands {
   }
 };
 
-// Inverse sources: lows and highs of a line.
-struct InvRows {
-  const int32_t *p;
-  int pitch, nlow;
-  __device__ int low(int line, int k) const { return p[int64_t(line) * pitch + k]; }
-  __device__ int high(int line, int k) const { return p[int64_t(line) * pitch + nlow + k]; }
-};
-struct InvBands {
-  const int32_t *ll32;
-  const int16_t *ll16, *hl, *lh, *hh;
-  int wl, wh;
-  __device__ int low(int c, int r) const {
-    if (c < wl) return ll32 ? ll32[int64_t(r) * wl + c] : int(ll16[int64_t(r) * wl + c]);
-    return hl[int64_t(r) * wh + (c - wl)];
-  }
-  __device__ int high(int c, int r) const {
-    if (c < wl) return lh[int64_t(r) * wl + c];
-    return hh[int64_t(r) * wh + (c - wl)];
-  }
-};
-// Inverse sinks: reconstructed samples.
-struct OutCols {
-  int32_t *p;
-  int pitch;
-  __device__ void operator()(int line, int pos, int v) const { p[int64_t(pos) * pitch + line] = v; }
-};
-struct OutRows {
-  int32_t *p;
-  int pitch;
-  __device__ void operator()(int line, int pos, int v) const { p[int64_t(line) * pitch + pos] = v; }
-};
-struct OutView {  // level-0 bytes, first n only, modulo 256
-  uint8_t *p;
-  int64_t n;
-  int pitch;
-  __device__ void operator()(int line, int pos, int v) const {
-    const int64_t o = int64_t(line) * pitch + pos;
-    if (o < n) p[o] = uint8_t(v);
-  }
-};
-
 // (context, target) capture of every predict step, for training: pair index
 // off + line * per_line + (i - 1) / 2.
 struct Capture {
@@ -332,7 +297,7 @@ __global__ __launch_bounds__(256) void lfwd_kernel(Src src, Sink sink, const Net
 #pragma unroll
     for (int j = 0; j < kCtx; ++j) e[j] = sE[(q + j) * LINES + li];
     const int base = (e[3] + e[4]) >> 1;
-    const int corr = correction_mfma(mn, e, base, lane);
+    const int corr = correction_mfma(mn, e, base);
     if (!valid) continue;
     const int x = sO[q * LINES + li];
     sD[q * LINES + li] = x - base - corr;
@@ -361,55 +326,6 @@ __global__ __launch_bounds__(256) void lfwd_kernel(Src src, Sink sink, const Net
     const int dr = sD[(i == N - 1 ? e2 : e2 + 1) * LINES + li];  // d(m(i+1))
     sink.low(line, i >> 1, x + ((dl + dr + 2) >> 2));
     if (i + 1 < N) sink.high(line, i >> 1, sD[(e2 + 1) * LINES + li]);
-  }
-}
-
-template <int LINES, int SEG, class Src, class Out>
-__global__ __launch_bounds__(256) void linv_kernel(Src src, Out out, const Net net, int N,
-                                                   int n_lines, int n_seg) {
-  using T = Tile<LINES, SEG>;
-  __shared__ int32_t sE[T::NE * LINES];
-  __shared__ uint32_t s_net[64];
-  int s0, l0;
-  tile_coords(n_seg, SEG, LINES, &s0, &l0);
-  const int tid = int(threadIdx.x);
-  stage_net(s_net, net);
-
-  // undo the update at the (mirrored) even positions s0-8 .. s0+SEG+6
-  for (int idx = tid; idx < T::NE * LINES; idx += T::kThreads) {
-    const int li = idx % LINES, e = idx / LINES, line = l0 + li;
-    int v = 0;
-    if (line < n_lines) {
-      const int p = mirror_pos(s0 - kHalo + 2 * e, N);
-      v = src.low(line, p >> 1);
-      if (N > 1) {
-        const int pl = p == 0 ? 1 : p - 1;
-        const int pr = p == N - 1 ? N - 2 : p + 1;
-        v -= (src.high(line, pl >> 1) + src.high(line, pr >> 1) + 2) >> 2;
-      }
-    }
-    sE[e * LINES + li] = v;
-  }
-  __syncthreads();
-
-  // owned positions: evens as rebuilt, odds by undoing the predict (the
-  // network on the matrix cores: uniform trip count per wavefront)
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const MfmaNet mn = mfma_net(s_net, net.b2, net.shift, lane);
-  for (int base0 = wave * 64; base0 < (SEG / 2) * LINES; base0 += T::kThreads) {
-    const int idx = base0 + lane;
-    const bool in = idx < (SEG / 2) * LINES;
-    const int li = in ? idx % LINES : 0, e2 = in ? idx / LINES : 0, line = l0 + li;
-    const int i = s0 + 2 * e2;
-    const bool valid = in && i < N && line < n_lines;
-    if (valid) out(line, i, sE[(e2 + 4) * LINES + li]);
-    const int q = e2 + 1;
-    int e[kCtx];
-#pragma unroll
-    for (int j = 0; j < kCtx; ++j) e[j] = sE[(q + j) * LINES + li];
-    const int base = (e[3] + e[4]) >> 1;
-    const int corr = correction_mfma(mn, e, base, lane);
-    if (valid && i + 1 < N) out(line, i + 1, src.high(line, i >> 1) + base + corr);
   }
 }
 
@@ -458,13 +374,431 @@ hipError_t col_fwd(Src src, Sink sink, const Net &net, int N, int lines, const C
   return hipGetLastError();
 }
 
-template <int LINES, int SEG, class Src, class Out>
-hipError_t inv_pass(Src src, Out out, const Net &net, int N, int lines, hipStream_t s) {
-  int n_seg;
-  unsigned grid;
-  if (!grid_for<LINES, SEG>(N, lines, &n_seg, &grid)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((linv_kernel<LINES, SEG, Src, Out>), dim3(grid), dim3(256), 0, s, src, out,
-                     net, N, lines, n_seg);
+// ------------------------------------------------ fused per-level kernels --
+// Protect and restore run one launch per level and direction.  A block owns
+// an Ht x kLvW rectangle of the level's sample grid (first row r0 and first
+// column c0, both even) and runs both 1-D passes of the level over it in
+// LDS, with the halos they need:
+//   forward: the row pass over the rows the column pass reads (even rows
+//     r0-8 .. r0+Ht+6, odd rows r0-1 .. r0+Ht-1), on columns
+//     c0-8 .. c0+kLvW+6; then the column pass on the owned columns;
+//   inverse: the column pass over columns c0-7 .. c0+kLvW+7 (rows
+//     r0-7 .. r0+Ht+7 loaded), then the row pass on the owned rows.
+// Rows and columns outside the level are loaded mirrored (whole-sample),
+// the extension the definition uses: the update and its inverse are
+// symmetric about each edge, the context reads mirrored samples by
+// definition, and a predict at a mirrored position outside the signal is
+// never used (the update of the first and last sample takes the mirrored
+// real neighbour instead).  Samples are updated in place in LDS: int16 in
+// the forward (every coefficient and intermediate of a byte input fits for
+// up to three levels), int32 in the inverse, which must reproduce the
+// definition for any fragment contents, also those no protect produces.
+// Predicts go in batches of 64, one per lane, so that each wavefront calls
+// the matrix-core network with every lane active.
+// Ht is 64 in the forward and 32 in the inverse, whose int32 samples take
+// twice the LDS (its row halo adds loads, not predicts).
+constexpr int kFwdH = 64, kInvH = 32, kLvW = 128;
+constexpr int kLvPitch = kLvW + 16;  // local column q <-> c0 - 8 + q; local row k <-> r0 - 8 + k
+static_assert(kLvW == 128, "the row passes give each lane two columns of a 128-column tile");
+
+// Tile loads: each thread keeps eight global loads in flight, then writes
+// them to LDS (load(idx) reads element idx of the tile, store(idx, v)
+// places it).
+template <int TOTAL, class Load, class Store>
+__device__ __forceinline__ void tile_load(const Load &load, const Store &store) {
+  constexpr int kU = 8;
+  for (int base = 0; base < TOTAL; base += 256 * kU) {
+    int v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int idx = base + u * 256 + int(threadIdx.x);
+      v[u] = idx < TOTAL ? load(idx) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int idx = base + u * 256 + int(threadIdx.x);
+      if (idx < TOTAL) store(idx, v[u]);
+    }
+  }
+}
+
+// Sources and sinks of the fused kernels.  quad(r, c, W, &ok) reads the
+// four samples c .. c+3 of row r (c a multiple of 4) with one vector load,
+// raw; ok says whether that form applies (every sample inside the row and
+// the buffer).  Where it does not, the load reads the start of the row
+// instead, so that the loads of a thread carry no branch and can all be in
+// flight together; the caller then reads single samples.  Only called where
+// the host set vec: the alignment holds, and every row start read this way
+// is inside its band (with vec unset a band may be empty, its pointer null).
+struct LvSrc8 {  // level-0 bytes, zero past n
+  const uint8_t *p;
+  int64_t n;
+  int pitch;
+  int vec;  // pitch and p 4-byte aligned, n >= 4
+  __device__ int operator()(int r, int c) const {
+    const int64_t o = int64_t(r) * pitch + c;
+    return o < n ? int(p[o]) : 0;
+  }
+  __device__ uint32_t quad(int r, int c, int W, bool *ok) const {
+    const int64_t o = int64_t(r) * pitch + c;
+    *ok = vec && c >= 0 && c + 4 <= W && o + 4 <= n;
+    return *reinterpret_cast<const uint32_t *>(p + (*ok ? o : 0));
+  }
+  // the raw quad as four int16 lanes
+  static __device__ uint2 widen(uint32_t w) {
+    return make_uint2(__builtin_amdgcn_perm(0u, w, 0x0c010c00u), __builtin_amdgcn_perm(0u, w, 0x0c030c02u));
+  }
+};
+struct LvSrc16 {  // an LL band of the previous level
+  const int16_t *p;
+  int pitch;
+  int vec;  // pitch a multiple of 4, p 8-byte aligned
+  __device__ int operator()(int r, int c) const { return p[int64_t(r) * pitch + c]; }
+  __device__ uint2 quad(int r, int c, int W, bool *ok) const {
+    *ok = vec && c >= 0 && c + 4 <= W;
+    return *reinterpret_cast<const uint2 *>(p + int64_t(r) * pitch + (*ok ? c : 0));
+  }
+  static __device__ uint2 widen(uint2 v) { return v; }
+};
+// The four bands of a level (LL: next level's input or the private
+// fragment); wl / wh: columns of the row lows / highs.
+struct LvBands {
+  int16_t *ll, *hl, *lh, *hh;
+  int wl, wh;
+};
+// Coefficient (r, c) of a level's interleaved grid: the band by the
+// parities; LL from int16 (the private fragment) or int32 (a level below).
+struct LvCoef {
+  const int16_t *ll16;
+  const int32_t *ll32;
+  const int16_t *hl, *lh, *hh;
+  int wl, wh;
+  int vec;  // H >= 2; wl, wh even; the int16 bands 4-byte and ll32 8-byte aligned
+  __device__ int operator()(int r, int c) const {
+    const int64_t rr = r >> 1, cc = c >> 1;
+    if (!(r & 1)) {
+      if (c & 1) return hl[rr * wh + cc];
+      return ll32 ? ll32[rr * wl + cc] : int(ll16[rr * wl + cc]);
+    }
+    return (c & 1) ? hh[rr * wh + cc] : lh[rr * wl + cc];
+  }
+  // Samples c .. c+3 of row r: two of the even-column band (a: int16 pair,
+  // or a32: int32 pair where the row is even and LL is int32) and two of the
+  // odd one (b).  The row's parity and LL's width are fixed per call site.
+  template <bool ODD, bool LL32>
+  __device__ void quad(int r, int c, int W, bool *ok, uint32_t *a, uint2 *a32, uint32_t *b) const {
+    *ok = vec && c >= 0 && c + 4 <= W;
+    const int64_t rr = r >> 1, cc = *ok ? (c >> 1) : 0;
+    if (ODD) {
+      *a = *reinterpret_cast<const uint32_t *>(lh + rr * wl + cc);
+      *b = *reinterpret_cast<const uint32_t *>(hh + rr * wh + cc);
+    } else {
+      if (LL32) *a32 = *reinterpret_cast<const uint2 *>(ll32 + rr * wl + cc);
+      else *a = *reinterpret_cast<const uint32_t *>(ll16 + rr * wl + cc);
+      *b = *reinterpret_cast<const uint32_t *>(hl + rr * wh + cc);
+    }
+  }
+};
+struct LvDst8 {  // level-0 bytes, first n only, modulo 256
+  uint8_t *p;
+  int64_t n;
+  int pitch;
+  __device__ void operator()(int r, int c, int v) const {
+    const int64_t o = int64_t(r) * pitch + c;
+    if (o < n) p[o] = uint8_t(v);
+  }
+};
+struct LvDst32 {
+  int32_t *p;
+  int pitch;
+  __device__ void operator()(int r, int c, int v) const { p[int64_t(r) * pitch + c] = v; }
+};
+
+template <class T>
+__device__ __forceinline__ void load_context(const T *at, int stride, int (&e)[kCtx]) {
+#pragma unroll
+  for (int j = 0; j < kCtx; ++j) e[j] = at[2 * j * stride];
+}
+
+template <class Src>
+__global__ __launch_bounds__(256) void lfwd_level_kernel(Src src, LvBands out, const Net net, int H,
+                                                         int W, int tiles_x) {
+  __shared__ int16_t X[(kFwdH + 16) * kLvPitch];
+  __shared__ uint32_t s_net[64];
+  constexpr int P = kLvPitch;
+  constexpr int kEvRows = kFwdH / 2 + 8;                // even local rows 0, 2, .., kFwdH+14
+  constexpr int kRows = kEvRows + kFwdH / 2 + 1;        // + odd local rows 7, 9, .., kFwdH+7
+  constexpr int kCols = kLvW + 15;                     // local columns 0 .. kLvW+14
+  const int tid = int(threadIdx.x);
+  const int r0 = int(blockIdx.x / unsigned(tiles_x)) * kFwdH;
+  const int c0 = int(blockIdx.x % unsigned(tiles_x)) * kLvW;
+  const auto local_row = [](int t) { return t < kEvRows ? 2 * t : 7 + 2 * (t - kEvRows); };
+  stage_net(s_net, net);
+  // tile loads: groups of 36 threads take a row, four samples each (local
+  // columns 0 .. 143); where a quad cannot be read whole, the block reads
+  // every sample of the tile singly instead
+  bool miss = !src.vec;
+  if (src.vec) {
+    const int slot = tid % 36, grp = tid / 36;  // 7 groups; threads 252 .. 255 idle
+    constexpr int kU = 4;
+    for (int t0 = 0; t0 < kRows; t0 += 7 * kU) {
+      decltype(src.quad(0, 0, 0, &miss)) v[kU];
+      bool ok[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int t = min(t0 + grp + 7 * u, kRows - 1);
+        v[u] = src.quad(mirror_pos(r0 - 8 + local_row(t), H), c0 - 8 + 4 * slot, W, &ok[u]);
+        ok[u] = ok[u] && grp < 7 && t0 + grp + 7 * u < kRows;
+        miss |= grp < 7 && t0 + grp + 7 * u < kRows && !ok[u];
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (ok[u])
+          *reinterpret_cast<uint2 *>(X + local_row(t0 + grp + 7 * u) * P + 4 * slot) = Src::widen(v[u]);
+    }
+  }
+  if (__syncthreads_or(miss)) {
+    tile_load<kRows * kCols>(
+        [&](int idx) {
+          const int t = idx / kCols, q = idx - t * kCols;
+          return src(mirror_pos(r0 - 8 + local_row(t), H), mirror_pos(c0 - 8 + q, W));
+        },
+        [&](int idx, int v) {
+          const int t = idx / kCols, q = idx - t * kCols;
+          X[local_row(t) * P + q] = int16_t(v);
+        });
+  }
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const MfmaNet mn = mfma_net(s_net, net.b2, net.shift, lane);
+
+  // row pass, predict: batch b < kRows takes row b at the owned odd columns
+  // (q = 9 + 2 lane); the last batches take the odd column q = 7 (c0 - 1)
+  // of 64 rows each
+  constexpr int kRowBatches = kRows + (kRows + 63) / 64;
+  for (int b = wave; b < kRowBatches; b += 4) {
+    int t = b, q = 9 + 2 * lane;
+    if (b >= kRows) {
+      t = (b - kRows) * 64 + lane;
+      q = 7;
+    }
+    const bool in = t < kRows;
+    const int k = local_row(in ? t : 0);
+    int e[kCtx];
+    load_context(X + k * P + q - 7, 1, e);
+    const int base = (e[3] + e[4]) >> 1;
+    const int corr = correction_mfma(mn, e, base);
+    const int i = c0 - 8 + q;
+    if (in && i > 0 && i < W) X[k * P + q] = int16_t(X[k * P + q] - base - corr);
+  }
+  __syncthreads();
+  // row pass, update at the owned even columns (q = 8 + 2 lane)
+  if (W > 1) {
+    for (int t = wave; t < kRows; t += 4) {
+      const int k = local_row(t), q = 8 + 2 * lane, c = c0 + 2 * lane;
+      if (c < W) {
+        int16_t *row = X + k * P;
+        const int dl = row[c == 0 ? q + 1 : q - 1];
+        const int dr = row[c == W - 1 ? q - 1 : q + 1];
+        row[q] = int16_t(row[q] + ((dl + dr + 2) >> 2));
+      }
+    }
+  }
+  __syncthreads();
+  // column pass, predict at the odd rows k = 7 (r0 - 1), 9, .., kFwdH+7 of
+  // the owned columns, 64 columns per batch
+  for (int b = wave; b < (kFwdH / 2 + 1) * 2; b += 4) {
+    const int k = 7 + 2 * (b >> 1), q = 8 + 64 * (b & 1) + lane;
+    int e[kCtx];
+    load_context(X + (k - 7) * P + q, P, e);
+    const int base = (e[3] + e[4]) >> 1;
+    const int corr = correction_mfma(mn, e, base);
+    const int i = r0 - 8 + k;
+    if (i > 0 && i < H && c0 - 8 + q < W) X[k * P + q] = int16_t(X[k * P + q] - base - corr);
+  }
+  __syncthreads();
+  // column pass, update at the owned even rows; each lane stores the band
+  // samples of the column pair c0 + 2 lane, +1 (band column c0/2 + lane)
+  const int64_t cc = c0 / 2 + lane;
+  for (int m = wave; m < kFwdH / 2; m += 4) {
+    const int k = 8 + 2 * m, r = r0 + 2 * m;
+    if (r >= H) break;
+    const int64_t rr = r >> 1;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = 8 + 2 * lane + h, c = c0 + 2 * lane + h;
+      if (c >= W) continue;
+      int v = X[k * P + q];
+      if (H > 1) {
+        const int dl = X[(r == 0 ? k + 1 : k - 1) * P + q];
+        const int dr = X[(r == H - 1 ? k - 1 : k + 1) * P + q];
+        v += (dl + dr + 2) >> 2;
+      }
+      if (h == 0) {
+        if (out.ll) out.ll[rr * out.wl + cc] = int16_t(v);
+      } else {
+        out.hl[rr * out.wh + cc] = int16_t(v);
+      }
+      if (r + 1 < H) {
+        const int16_t d = X[(k + 1) * P + q];
+        if (h == 0) out.lh[rr * out.wl + cc] = d;
+        else out.hh[rr * out.wh + cc] = d;
+      }
+    }
+  }
+}
+
+// Inverse tile loads in quads: local rows 1 .. kInvH+15 (global rows
+// r0-7 ..), local columns 0 .. 143.  Local row 1 + t holds an even global
+// row when t is odd (mirroring keeps parity), so the two parities run as
+// separate passes, each with fixed bands.  Returns whether a quad was
+// missed (the caller then reads the tile singly).
+template <bool ODD, bool LL32>
+__device__ __forceinline__ bool inv_quads_parity(const LvCoef &src, int32_t *Z, int r0, int c0, int H,
+                                                 int W) {
+  constexpr int P = kLvPitch, kR = kInvH + 15;
+  const int tid = int(threadIdx.x), slot = tid % 36, grp = tid / 36;
+  bool miss = false;
+  // rows of this parity: t = t_first + 2 i
+  constexpr int t_first = ODD ? 0 : 1;
+  constexpr int n_rows = (kR - t_first + 1) / 2;
+  constexpr int kU = 4;
+  for (int i0 = 0; i0 < n_rows; i0 += 7 * kU) {
+    uint32_t a[kU], b[kU];
+    uint2 a32[kU];
+    bool ok[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = min(i0 + grp + 7 * u, n_rows - 1);
+      src.quad<ODD, LL32>(mirror_pos(r0 - 7 + t_first + 2 * i, H), c0 - 8 + 4 * slot, W, &ok[u], &a[u],
+                          &a32[u], &b[u]);
+      const bool mine = grp < 7 && i0 + grp + 7 * u < n_rows;
+      miss |= mine && !ok[u];
+      ok[u] = ok[u] && mine;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (!ok[u]) continue;
+      const int t = t_first + 2 * (i0 + grp + 7 * u);
+      const int b0 = int(b[u] << 16) >> 16, b1 = int(b[u]) >> 16;
+      int a0, a1;
+      if (!ODD && LL32) {
+        a0 = int(a32[u].x);
+        a1 = int(a32[u].y);
+      } else {
+        a0 = int(a[u] << 16) >> 16;
+        a1 = int(a[u]) >> 16;
+      }
+      *reinterpret_cast<int4 *>(Z + (1 + t) * P + 4 * slot) = make_int4(a0, b0, a1, b1);
+    }
+  }
+  return miss;
+}
+
+template <bool LL32>
+__device__ __forceinline__ bool inv_tile_quads(const LvCoef &src, int32_t *Z, int r0, int c0, int H,
+                                               int W) {
+  const bool m0 = inv_quads_parity<false, LL32>(src, Z, r0, c0, H, W);
+  const bool m1 = inv_quads_parity<true, LL32>(src, Z, r0, c0, H, W);
+  return m0 || m1;
+}
+
+template <class Dst>
+__global__ __launch_bounds__(256) void linv_level_kernel(LvCoef src, Dst dst, const Net net, int H,
+                                                         int W, int tiles_x) {
+  __shared__ int32_t Z[(kInvH + 16) * kLvPitch];
+  __shared__ uint32_t s_net[64];
+  constexpr int P = kLvPitch;
+  constexpr int kR = kInvH + 15, kC = kLvW + 15;  // local rows / columns 1 .. 15 + tile
+  const int tid = int(threadIdx.x);
+  const int r0 = int(blockIdx.x / unsigned(tiles_x)) * kInvH;
+  const int c0 = int(blockIdx.x % unsigned(tiles_x)) * kLvW;
+  stage_net(s_net, net);
+  // tile loads as in the forward: local rows 1 .. kInvH+15, local columns
+  // 0 .. 143 in quads, or every sample singly where a quad is missing
+  bool miss = !src.vec;
+  if (src.vec) miss = src.ll32 ? inv_tile_quads<true>(src, Z, r0, c0, H, W)
+                               : inv_tile_quads<false>(src, Z, r0, c0, H, W);
+  if (__syncthreads_or(miss)) {
+    tile_load<kR * kC>(
+        [&](int idx) {
+          const int t = idx / kC, q = 1 + idx - t * kC;
+          return src(mirror_pos(r0 - 7 + t, H), mirror_pos(c0 - 8 + q, W));
+        },
+        [&](int idx, int v) {
+          const int t = idx / kC, q = 1 + idx - t * kC;
+          Z[(1 + t) * P + q] = v;
+        });
+  }
+  __syncthreads();
+  // column pass, undo the update at the even rows k = 2 .. kInvH+14
+  if (H > 1) {
+    constexpr int kEv = kInvH / 2 + 7;
+    for (int idx = tid; idx < kEv * kC; idx += 256) {
+      const int t = idx / kC, k = 2 + 2 * t, q = 1 + idx - t * kC;
+      Z[k * P + q] -= (Z[(k - 1) * P + q] + Z[(k + 1) * P + q] + 2) >> 2;
+    }
+  }
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const MfmaNet mn = mfma_net(s_net, net.b2, net.shift, lane);
+  // column pass, undo the predict at the owned odd rows k = 9 .. kInvH+7,
+  // every loaded column
+  constexpr int kSamples = (kInvH / 2) * kC;
+  for (int b = wave; b < (kSamples + 63) / 64; b += 4) {
+    const int s = b * 64 + lane;
+    const bool in = s < kSamples;
+    const int m = in ? s / kC : 0, q = in ? 1 + s - m * kC : 1, k = 9 + 2 * m;
+    int e[kCtx];
+    load_context(Z + (k - 7) * P + q, P, e);
+    const int base = (e[3] + e[4]) >> 1;
+    const int corr = correction_mfma(mn, e, base);
+    if (in && r0 - 8 + k < H) Z[k * P + q] += base + corr;
+  }
+  __syncthreads();
+  // row pass, undo the update at the even columns q = 2 .. kLvW+14 of the
+  // owned rows
+  if (W > 1) {
+    constexpr int kEv = kLvW / 2 + 7;
+    for (int idx = tid; idx < kInvH * kEv; idx += 256) {
+      const int t = idx / kEv, k = 8 + t, q = 2 + 2 * (idx - t * kEv);
+      int32_t *row = Z + k * P;
+      row[q] -= (row[q - 1] + row[q + 1] + 2) >> 2;
+    }
+  }
+  __syncthreads();
+  // row pass, undo the predict at the owned odd columns (q = 9 + 2 lane) and
+  // store the column pair c0 + 2 lane, +1 of each owned row
+  for (int t = wave; t < kInvH; t += 4) {
+    const int k = 8 + t, r = r0 + t;
+    if (r >= H) break;
+    const int q = 9 + 2 * lane, c = c0 + 2 * lane;
+    int e[kCtx];
+    load_context(Z + k * P + q - 7, 1, e);
+    const int base = (e[3] + e[4]) >> 1;
+    const int corr = correction_mfma(mn, e, base);
+    if (c < W) dst(r, c, Z[k * P + q - 1]);
+    if (c + 1 < W) dst(r, c + 1, Z[k * P + q] + base + corr);
+  }
+}
+
+template <class Src>
+hipError_t fwd_level(Src src, const LvBands &out, const Net &net, int h, int w, hipStream_t s) {
+  const int tx = (w + kLvW - 1) / kLvW, ty = (h + kFwdH - 1) / kFwdH;
+  const int64_t grid = int64_t(tx) * ty;
+  if (grid <= 0 || grid > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((lfwd_level_kernel<Src>), dim3(unsigned(grid)), dim3(256), 0, s, src, out, net,
+                     h, w, tx);
+  return hipGetLastError();
+}
+
+template <class Dst>
+hipError_t inv_level(const LvCoef &src, Dst dst, const Net &net, int h, int w, hipStream_t s) {
+  const int tx = (w + kLvW - 1) / kLvW, ty = (h + kInvH - 1) / kInvH;
+  const int64_t grid = int64_t(tx) * ty;
+  if (grid <= 0 || grid > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((linv_level_kernel<Dst>), dim3(unsigned(grid)), dim3(256), 0, s, src, dst, net,
+                     h, w, tx);
   return hipGetLastError();
 }
 
@@ -475,8 +809,10 @@ struct LearnedLevel {
   const int16_t *chl, *clh, *chh;
 };
 
-// Forward over all levels.  T: int32 H x W scratch; B: int32 h1 x w1
-// scratch for LL_1 .. LL_{L-1}; ll_out: int16 LL_L (null: discard).
+// Forward over all levels as separate 1-D passes, for the training-pair
+// capture (the pairs are taken in each pass's own order).  T: int32 H x W
+// scratch; B: int32 h1 x w1 scratch for LL_1 .. LL_{L-1}; ll_out: int16 LL_L
+// (null: discard).
 hipError_t learned_forward(const uint8_t *in, int64_t n, int W, int L, const LearnedLevel *lv,
                            int32_t *T, int32_t *B, int16_t *ll_out, const Net &net,
                            const int64_t *cap_off, uint2 *cap_ctx, int32_t *cap_tgt,
@@ -499,19 +835,47 @@ hipError_t learned_forward(const uint8_t *in, int64_t n, int W, int L, const Lea
   return hipSuccess;
 }
 
-// Inverse over all levels, from int16 LL_L (already decrypted) and the bands.
-hipError_t learned_inverse(const int16_t *ll_in, const LearnedLevel *lv, int L, int32_t *T,
-                           int32_t *B, uint8_t *out, int64_t n, int W, const Net &net,
-                           hipStream_t s) {
+inline bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Protect over all levels with the fused kernels.  LL_1 goes to T16, LL_2
+// to B16 (int16, each level's own width), LL_L to ll_out.
+hipError_t learned_protect_levels(const uint8_t *in, int64_t n, int W, int L, const LearnedLevel *lv,
+                                  int16_t *T16, int16_t *B16, int16_t *ll_out, const Net &net,
+                                  hipStream_t s) {
+  for (int l = 1; l <= L; ++l) {
+    const LearnedLevel &v = lv[l - 1];
+    const int wl = (v.w + 1) / 2;
+    const LvBands bands{l == L ? ll_out : (l == 1 ? T16 : B16), v.hl, v.lh, v.hh, wl, v.w - wl};
+    const int16_t *ll_in = l == 2 ? T16 : B16;
+    const hipError_t e =
+        l == 1 ? fwd_level(LvSrc8{in, n, W, W % 4 == 0 && n >= 4 && aligned(in, 4)}, bands, net, v.h,
+                           v.w, s)
+               : fwd_level(LvSrc16{ll_in, v.w, v.w % 4 == 0 && aligned(ll_in, 8)}, bands, net, v.h,
+                           v.w, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Restore over all levels, from int16 LL_L (already decrypted) and the bands;
+// LL_1 in T32, LL_2 in B32 (int32: fragments no protect produced may leave
+// int16).
+hipError_t learned_restore_levels(const int16_t *ll_in, const LearnedLevel *lv, int L, int32_t *T32,
+                                  int32_t *B32, uint8_t *out, int64_t n, int W, const Net &net,
+                                  hipStream_t s) {
   for (int l = L; l >= 1; --l) {
     const LearnedLevel &v = lv[l - 1];
-    const int h = v.h, w = v.w, wl = (w + 1) / 2;
-    InvBands bands{l < L ? B : nullptr, l == L ? ll_in : nullptr, v.chl, v.clh, v.chh, wl, w - wl};
-    hipError_t e = inv_pass<kColLines, kColSeg>(bands, OutCols{T, w}, net, h, w, s);
-    if (e != hipSuccess) return e;
-    InvRows rows{T, w, wl};
-    e = (l == 1) ? inv_pass<1, kRowSeg>(rows, OutView{out, n, W}, net, w, h, s)
-                 : inv_pass<1, kRowSeg>(rows, OutRows{B, w}, net, w, h, s);
+    const int wl = (v.w + 1) / 2;
+    LvCoef coef{l == L ? ll_in : nullptr, l == L ? nullptr : (l == 1 ? T32 : B32),
+                v.chl, v.clh, v.chh, wl, v.w - wl, 0};
+    // (two rows at least: the quads take each row's parity from its
+    // unmirrored index, which mirroring keeps only then)
+    coef.vec = v.h >= 2 && wl % 2 == 0 && (v.w - wl) % 2 == 0 && aligned(coef.ll16, 4) &&
+               aligned(coef.ll32, 8) && aligned(coef.hl, 4) && aligned(coef.lh, 4) &&
+               aligned(coef.hh, 4);
+    const hipError_t e =
+        l == 1 ? inv_level(coef, LvDst8{out, n, W}, net, v.h, v.w, s)
+               : inv_level(coef, LvDst32{l == 2 ? T32 : B32, v.w}, net, v.h, v.w, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -858,9 +1222,9 @@ int dwtfrag_protect_learned(const uint8_t *in, uint64_t n, uint32_t width, uint3
   fill_levels(g, pub, nullptr, lv);
   char *ws = static_cast<char *>(workspace);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (learned_forward(in, int64_t(n), g.W, g.L, lv, reinterpret_cast<int32_t *>(ws + g.off_T),
-                      reinterpret_cast<int32_t *>(ws + g.off_B), reinterpret_cast<int16_t *>(priv),
-                      net, nullptr, nullptr, nullptr, st) != hipSuccess)
+  if (learned_protect_levels(in, int64_t(n), g.W, g.L, lv, reinterpret_cast<int16_t *>(ws + g.off_T),
+                             reinterpret_cast<int16_t *>(ws + g.off_B),
+                             reinterpret_cast<int16_t *>(priv), net, st) != hipSuccess)
     return DWTFRAG_EDEVICE;
   if (launch_ctr(priv, priv, g.priv_bytes, k, 0, st) != hipSuccess) return DWTFRAG_EDEVICE;
   return DWTFRAG_OK;
@@ -886,10 +1250,10 @@ int dwtfrag_restore_learned(const uint8_t *priv, const int16_t *pub, uint64_t n,
   hipStream_t st = static_cast<hipStream_t>(stream);
   uint8_t *ll = reinterpret_cast<uint8_t *>(ws + g.off_LL);
   if (launch_ctr(priv, ll, g.priv_bytes, k, 0, st) != hipSuccess) return DWTFRAG_EDEVICE;
-  if (learned_inverse(reinterpret_cast<const int16_t *>(ll), lv, g.L,
-                      reinterpret_cast<int32_t *>(ws + g.off_T),
-                      reinterpret_cast<int32_t *>(ws + g.off_B), out, int64_t(n), g.W, net,
-                      st) != hipSuccess)
+  if (learned_restore_levels(reinterpret_cast<const int16_t *>(ll), lv, g.L,
+                             reinterpret_cast<int32_t *>(ws + g.off_T),
+                             reinterpret_cast<int32_t *>(ws + g.off_B), out, int64_t(n), g.W, net,
+                             st) != hipSuccess)
     return DWTFRAG_EDEVICE;
   return DWTFRAG_OK;
 }

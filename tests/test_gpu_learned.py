@@ -50,12 +50,15 @@ def _restore(priv, pub, n, width, levels, key, nonce, gnet):
     return out.cpu().numpy().tobytes()
 
 
-# (n, width, levels): degenerate and ragged shapes; rows spanning several
-# 2048-sample segments; columns spanning several 64 x 64 tiles.
+# (n, width, levels): degenerate and ragged shapes; levels spanning several
+# 64 x 128 tiles of the protect / restore kernels in either direction, with
+# ragged last tiles and odd dimensions at every level; rows spanning several
+# 2048-sample segments of the training-pair capture.
 CASES = [
     (1, 1, 1), (2, 1, 2), (2, 2, 1), (5, 2, 3), (9, 3, 2), (100, 7, 3), (1000, 1, 3),
     (4097, 64, 3), (12345, 97, 2), (200 * 130 - 17, 130, 3), (70 * 2049, 2049, 1),
-    (3 * 4500 + 11, 4500, 3), (262144, 512, 1), (300000, 1031, 2),
+    (3 * 4500 + 11, 4500, 3), (262144, 512, 1), (300000, 1031, 2), (333 * 261 - 5, 261, 3),
+    (129 * 257, 257, 2),
 ]
 
 
