@@ -572,24 +572,30 @@ __global__ __launch_bounds__(256) void lfwd_level_kernel(Src src, LvBands out, c
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const MfmaNet mn = mfma_net(s_net, net.b2, net.shift, lane);
 
-  // row pass, predict: batch b < kRows takes row b at the owned odd columns
-  // (q = 9 + 2 lane); the last batches take the odd column q = 7 (c0 - 1)
-  // of 64 rows each
-  constexpr int kRowBatches = kRows + (kRows + 63) / 64;
-  for (int b = wave; b < kRowBatches; b += 4) {
-    int t = b, q = 9 + 2 * lane;
-    if (b >= kRows) {
-      t = (b - kRows) * 64 + lane;
-      q = 7;
+  // row pass, predict: a batch per row at the owned odd columns (q = 9 +
+  // 2 lane), then batches of 64 rows at the odd column q = 7 (c0 - 1), on
+  // the waves the row batches leave least loaded
+  {
+    const int q = 9 + 2 * lane;
+    const bool col_ok = c0 + 1 + 2 * lane < W;
+    for (int t = wave; t < kRows; t += 4) {
+      int16_t *row = X + local_row(t) * P;
+      int e[kCtx];
+      load_context(row + q - 7, 1, e);
+      const int base = (e[3] + e[4]) >> 1;
+      const int corr = correction_mfma(mn, e, base);
+      if (col_ok) row[q] = int16_t(row[q] - base - corr);
     }
-    const bool in = t < kRows;
-    const int k = local_row(in ? t : 0);
-    int e[kCtx];
-    load_context(X + k * P + q - 7, 1, e);
-    const int base = (e[3] + e[4]) >> 1;
-    const int corr = correction_mfma(mn, e, base);
-    const int i = c0 - 8 + q;
-    if (in && i > 0 && i < W) X[k * P + q] = int16_t(X[k * P + q] - base - corr);
+    for (int b = (wave + 4 - kRows % 4) % 4; b < (kRows + 63) / 64; b += 4) {
+      const int t = b * 64 + lane;
+      const bool in = t < kRows;
+      int16_t *at = X + local_row(in ? t : 0) * P + 7;
+      int e[kCtx];
+      load_context(at - 7, 1, e);
+      const int base = (e[3] + e[4]) >> 1;
+      const int corr = correction_mfma(mn, e, base);
+      if (in && c0 > 0) *at = int16_t(*at - base - corr);
+    }
   }
   __syncthreads();
   // row pass, update at the owned even columns (q = 8 + 2 lane)
@@ -743,17 +749,29 @@ __global__ __launch_bounds__(256) void linv_level_kernel(LvCoef src, Dst dst, co
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const MfmaNet mn = mfma_net(s_net, net.b2, net.shift, lane);
   // column pass, undo the predict at the owned odd rows k = 9 .. kInvH+7,
-  // every loaded column
-  constexpr int kSamples = (kInvH / 2) * kC;
-  for (int b = wave; b < (kSamples + 63) / 64; b += 4) {
-    const int s = b * 64 + lane;
-    const bool in = s < kSamples;
-    const int m = in ? s / kC : 0, q = in ? 1 + s - m * kC : 1, k = 9 + 2 * m;
+  // every loaded column (1 .. 143): per group of four rows, two batches of 64
+  // columns per row, then one batch of the last 15 columns of the four rows
+  static_assert(kC == 143 && (kInvH / 2) % 4 == 0, "column batches of the inverse tile");
+  constexpr int kGroups = kInvH / 2 / 4, kPerGroup = 9;
+  for (int b = wave; b < kGroups * kPerGroup; b += 4) {
+    const int g = b / kPerGroup, j = b - g * kPerGroup;  // wave-uniform
+    int k, q;
+    bool in = true;
+    if (j < 8) {
+      k = 9 + 2 * (4 * g + (j >> 1));
+      q = 1 + 64 * (j & 1) + lane;
+    } else {
+      const int rsub = lane >> 4, csub = lane & 15;
+      in = rsub < 4 && csub < 15;
+      k = 9 + 2 * (4 * g + (in ? rsub : 0));
+      q = 129 + (in ? csub : 0);
+    }
+    int32_t *at = Z + k * P + q;
     int e[kCtx];
-    load_context(Z + (k - 7) * P + q, P, e);
+    load_context(at - 7 * P, P, e);
     const int base = (e[3] + e[4]) >> 1;
     const int corr = correction_mfma(mn, e, base);
-    if (in && r0 - 8 + k < H) Z[k * P + q] += base + corr;
+    if (in && r0 - 8 + k < H) *at += base + corr;
   }
   __syncthreads();
   // row pass, undo the update at the even columns q = 2 .. kLvW+14 of the
