@@ -19,7 +19,7 @@ hipError_t launch_inv(int L, int C1, bool u8out, const int16_t *llin, const int1
 hipError_t launch_ctr(const uint8_t *in, uint8_t *out, uint64_t nbytes, const AesKey &key,
                       uint64_t first_block, hipStream_t s);
 int fwd_waves_per_cu(int L, int C1, bool u8in);
-int inv_waves_per_cu(int L, int C1, bool u8out, bool split);
+int inv_waves_per_cu(int L, int C1, bool u8out);
 
 static constexpr AesTables kHostTables = make_aes_tables();
 
@@ -122,13 +122,12 @@ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 // Wavefronts the current device keeps resident at once for the kernel of a
 // stage: compute units x resident wavefronts per CU (queried once per device
 // and kernel variant; falls back to 256 x 16 if the queries fail).
-int64_t device_slots(bool forward, int L, int C1, bool bytes, bool split) {
-  constexpr int kDev = 16, kVar = 2 * 5 * 2 * 2 * 2;
+int64_t device_slots(bool forward, int L, int C1, bool bytes) {
+  constexpr int kDev = 16, kVar = 2 * 5 * 2 * 2;
   static std::atomic<int> cache[kDev][kVar];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDev) dev = -1;
-  const int var = (((forward ? 1 : 0) * 5 + L) * 4 + (C1 == 16 ? 2 : 0) + (bytes ? 1 : 0)) * 2 +
-                  (split ? 1 : 0);
+  const int var = ((forward ? 1 : 0) * 5 + L) * 4 + (C1 == 16 ? 2 : 0) + (bytes ? 1 : 0);
   if (dev >= 0) {
     const int v = cache[dev][var].load(std::memory_order_relaxed);
     if (v > 0) return v;
@@ -136,7 +135,7 @@ int64_t device_slots(bool forward, int L, int C1, bool bytes, bool split) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev < 0 ? 0 : dev) != hipSuccess)
     cus = 0;
-  const int per_cu = forward ? fwd_waves_per_cu(L, C1, bytes) : inv_waves_per_cu(L, C1, bytes, split);
+  const int per_cu = forward ? fwd_waves_per_cu(L, C1, bytes) : inv_waves_per_cu(L, C1, bytes);
   const int slots = (cus > 0 && per_cu > 0) ? cus * per_cu : 256 * 16;
   if (dev >= 0) cache[dev][var].store(slots, std::memory_order_relaxed);
   return slots;
@@ -223,9 +222,7 @@ int plan_stage(const Geometry &g, int s, bool forward, const dwtfrag_launch *lau
     // A launch of its own whose grid stays within one wavefront per SIMD
     // even at one unit per segment takes one unit per segment: the extra
     // halo rows run on otherwise idle SIMDs and each stream is shorter.
-    // a byte-output restore of at least 16 MiB runs as the two-launch form
-    const bool split = !forward && s == 0 && g.n >= (uint64_t(1) << 24);
-    const int64_t slots = device_slots(forward, L, C1, s == 0, split);
+    const int64_t slots = device_slots(forward, L, C1, s == 0);
     n_seg = std::max<int64_t>(1, slots / P->n_win);
     const int min_units = (alone && int64_t(P->units) * P->n_win <= device_simds()) ? 1 : 2;
     n_seg = std::min<int64_t>(n_seg, std::max(1, P->units / min_units));

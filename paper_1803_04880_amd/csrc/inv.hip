@@ -879,15 +879,10 @@ int inv_batch_blocks_per_cu() {
 }
 
 // Resident wavefronts per CU of the inverse kernel for (L, C1).
-// split: the stage will run as the two-launch restore, whose packed kernel
-// (the FAST-only form) holds more wavefronts than the one-launch kernel.
-int inv_waves_per_cu(int L, int C1, bool u8out, bool split) {
+int inv_waves_per_cu(int L, int C1, bool u8out) {
   const void *fn = nullptr;
-#define DWTFRAG_FN(LL, CC)                                                                  \
-  if (L == LL && C1 == CC)                                                                  \
-    fn = (u8out && split) ? (CC == 8 ? reinterpret_cast<const void *>(&inv_split_pk8<LL, true>)  \
-                                     : reinterpret_cast<const void *>(&inv_split_pk16<LL, true>)) \
-         : u8out ? inv_fn<LL, CC, true>() : inv_fn<LL, CC, false>();
+#define DWTFRAG_FN(LL, CC) \
+  if (L == LL && C1 == CC) fn = u8out ? inv_fn<LL, CC, true>() : inv_fn<LL, CC, false>();
   DWTFRAG_FN(1, 8) DWTFRAG_FN(2, 8) DWTFRAG_FN(3, 8)
   DWTFRAG_FN(1, 16) DWTFRAG_FN(2, 16) DWTFRAG_FN(3, 16) DWTFRAG_FN(4, 16)
 #undef DWTFRAG_FN

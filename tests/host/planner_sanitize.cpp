@@ -24,7 +24,7 @@ hipError_t launch_fwd_batch(const BatchItem *, const int2 *, int64_t, BatchCount
 hipError_t launch_inv_batch(const BatchItem *, const int2 *, int64_t, BatchCounters *, int,
                             hipStream_t) { return hipErrorInvalidValue; }
 int fwd_waves_per_cu(int L, int C1, bool) { return C1 == 16 ? 8 : 12 + L % 2; }
-int inv_waves_per_cu(int L, int C1, bool, bool split) { return C1 == 16 ? 8 + 4 * split : 16 - L % 2; }
+int inv_waves_per_cu(int L, int C1, bool) { return C1 == 16 ? 8 : 16 - L % 2; }
 int fwd_batch_blocks_per_cu() { return 2; }
 int inv_batch_blocks_per_cu() { return 2; }
 }  // namespace dwtfrag
