@@ -123,11 +123,24 @@ __device__ __forceinline__ MfmaNet mfma_net(const uint32_t *s_net, int b2, int s
   return m;
 }
 
-__device__ __forceinline__ int correction_mfma(const MfmaNet &m, const int (&e)[kCtx], int base) {
+// v_mad_i32_i24 as one instruction: the products of the output layer are
+// chained through it (the compiler would otherwise regroup four products as
+// three multiplies, a multiply-add and a three-input add).
+__device__ __forceinline__ int mad24(int a, int b, int c) {
+  int r;
+  asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
+// Eight int8 context bytes (c_0 in the low byte) of int32 samples.
+__device__ __forceinline__ long pack_context(const int (&e)[kCtx], int base) {
   int c[kCtx];
 #pragma unroll
   for (int j = 0; j < kCtx; ++j) c[j] = clamp_i(e[j] - base, -128, 127);
-  const long b = long(pack4(c[0], c[1], c[2], c[3])) | (long(pack4(c[4], c[5], c[6], c[7])) << 32);
+  return long(pack4(c[0], c[1], c[2], c[3])) | (long(pack4(c[4], c[5], c[6], c[7])) << 32);
+}
+
+__device__ __forceinline__ int correction_packed(const MfmaNet &m, long b) {
   // p[g]: this lane's quarter of the output sum of group g's sample l % 16
   // (its four hidden units 4q..4q+3, q = l / 16); the four products are
   // independent, so they are all issued before the first result is read
@@ -137,9 +150,9 @@ __device__ __forceinline__ int correction_mfma(const MfmaNet &m, const int (&e)[
   int p[4];
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
-    int sum = 0;
+    int sum = __mul24(clamp_i(d[g][0], 0, 0x7fffff), m.w2[0]);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) sum += clamp_i(d[g][r], 0, 0x7fffff) * m.w2[r];
+    for (int r = 1; r < 4; ++r) sum = mad24(clamp_i(d[g][r], 0, 0x7fffff), m.w2[r], sum);
     p[g] = sum;
   }
   // Lane l needs group q's total: the sum of p[q] over lanes s, s+16, s+32,
@@ -155,6 +168,32 @@ __device__ __forceinline__ int correction_mfma(const MfmaNet &m, const int (&e)[
   const auto s01 = __builtin_amdgcn_permlane16_swap(k0, k1, false, false);
   const int mine = int(s01[0] + s01[1]);
   return clamp_i((mine + m.b2) >> m.shift, -255, 255);
+}
+
+__device__ __forceinline__ int correction_mfma(const MfmaNet &m, const int (&e)[kCtx], int base) {
+  return correction_packed(m, pack_context(e, base));
+}
+
+// The context of eight int16 samples at[0], at[2 s], .., at[14 s] in packed
+// 16-bit arithmetic: base = floor((at[6 s] + at[8 s]) / 2) is returned
+// through *base; the differences saturate at the int16 range, which leaves
+// their clamp to [-128, 127] unchanged, and the bytes are gathered by two
+// permutes.
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ long context16(const int16_t *at, int s, int *base) {
+  const s16x2 e01 = {at[0], at[2 * s]}, e23 = {at[4 * s], at[6 * s]};
+  const s16x2 e45 = {at[8 * s], at[10 * s]}, e67 = {at[12 * s], at[14 * s]};
+  const int bs = (int(e23.y) + int(e45.x)) >> 1;
+  *base = bs;
+  const s16x2 b2 = {short(bs), short(bs)}, lo = {-128, -128}, hi = {127, 127};
+  const auto cl = [&](s16x2 v) {
+    return __builtin_bit_cast(
+        uint32_t, __builtin_elementwise_min(__builtin_elementwise_max(__builtin_elementwise_sub_sat(v, b2), lo), hi));
+  };
+  const uint32_t a = __builtin_amdgcn_perm(cl(e23), cl(e01), 0x06040200u);
+  const uint32_t b = __builtin_amdgcn_perm(cl(e67), cl(e45), 0x06040200u);
+  return long(a) | (long(b) << 32);
 }
 
 // Stage the network in LDS (one copy per block) for mfma_net.
@@ -580,20 +619,16 @@ __global__ __launch_bounds__(256) void lfwd_level_kernel(Src src, LvBands out, c
     const bool col_ok = c0 + 1 + 2 * lane < W;
     for (int t = wave; t < kRows; t += 4) {
       int16_t *row = X + local_row(t) * P;
-      int e[kCtx];
-      load_context(row + q - 7, 1, e);
-      const int base = (e[3] + e[4]) >> 1;
-      const int corr = correction_mfma(mn, e, base);
+      int base;
+      const int corr = correction_packed(mn, context16(row + q - 7, 1, &base));
       if (col_ok) row[q] = int16_t(row[q] - base - corr);
     }
     for (int b = (wave + 4 - kRows % 4) % 4; b < (kRows + 63) / 64; b += 4) {
       const int t = b * 64 + lane;
       const bool in = t < kRows;
       int16_t *at = X + local_row(in ? t : 0) * P + 7;
-      int e[kCtx];
-      load_context(at - 7, 1, e);
-      const int base = (e[3] + e[4]) >> 1;
-      const int corr = correction_mfma(mn, e, base);
+      int base;
+      const int corr = correction_packed(mn, context16(at - 7, 1, &base));
       if (in && c0 > 0) *at = int16_t(*at - base - corr);
     }
   }
@@ -615,10 +650,8 @@ __global__ __launch_bounds__(256) void lfwd_level_kernel(Src src, LvBands out, c
   // the owned columns, 64 columns per batch
   for (int b = wave; b < (kFwdH / 2 + 1) * 2; b += 4) {
     const int k = 7 + 2 * (b >> 1), q = 8 + 64 * (b & 1) + lane;
-    int e[kCtx];
-    load_context(X + (k - 7) * P + q, P, e);
-    const int base = (e[3] + e[4]) >> 1;
-    const int corr = correction_mfma(mn, e, base);
+    int base;
+    const int corr = correction_packed(mn, context16(X + (k - 7) * P + q, P, &base));
     const int i = r0 - 8 + k;
     if (i > 0 && i < H && c0 - 8 + q < W) X[k * P + q] = int16_t(X[k * P + q] - base - corr);
   }
