@@ -262,7 +262,10 @@ int dwtfrag_learned_geometry(uint64_t n, uint32_t width, uint32_t levels,
 
 /* dwtfrag_protect with the learned predict step.
  *   predictor  HOST pointer, read before return; limits above (else EINVAL)
- *   workspace  device, >= workspace_bytes of dwtfrag_learned_geometry */
+ *   workspace  device, >= workspace_bytes of dwtfrag_learned_geometry; holds
+ *              the intermediate LL bands until the call's work on `stream` has
+ *              completed, so calls that can overlap (other streams) need
+ *              workspaces of their own; the same holds for the restore */
 int dwtfrag_protect_learned(const uint8_t *in, uint64_t n, uint32_t width, uint32_t levels,
                             const uint8_t key[16], const uint8_t nonce[16],
                             const dwtfrag_predictor *predictor,
