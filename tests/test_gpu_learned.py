@@ -76,7 +76,10 @@ def test_learned_protect_matches_oracle_and_roundtrips(n, width, levels):
     assert _restore(priv, pub, n, width, levels, key, nonce, gnet) == buf.tobytes()
 
 
-@pytest.mark.parametrize("n,width,levels", [(9, 3, 2), (12345, 97, 3), (200 * 130 - 17, 130, 2)])
+# The last two take the restore's vector tile loads (even band widths at
+# every level), with int32 intermediate LL bands between levels.
+@pytest.mark.parametrize("n,width,levels", [(9, 3, 2), (12345, 97, 3), (200 * 130 - 17, 130, 2),
+                                            (64 * 256, 256, 3), (300 * 512 - 100, 512, 2)])
 def test_learned_restore_of_arbitrary_fragments(n, width, levels):
     rng = np.random.default_rng(3 * n + levels)
     g = fragment.geometry(n, width, levels)
