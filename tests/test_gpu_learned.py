@@ -58,7 +58,7 @@ CASES = [
     (1, 1, 1), (2, 1, 2), (2, 2, 1), (5, 2, 3), (9, 3, 2), (100, 7, 3), (1000, 1, 3),
     (4097, 64, 3), (12345, 97, 2), (200 * 130 - 17, 130, 3), (70 * 2049, 2049, 1),
     (3 * 4500 + 11, 4500, 3), (262144, 512, 1), (300000, 1031, 2), (333 * 261 - 5, 261, 3),
-    (129 * 257, 257, 2),
+    (129 * 257, 257, 2), (3 * 20000 + 7, 20000, 2), (5000 * 4 + 1, 4, 3), (257 * 516, 516, 3),
 ]
 
 
