@@ -912,8 +912,11 @@ def run_learned(args):
     nimg = args.images or synth.LEARNED_IMAGES
     W, L, n = 4096, 3, 4096 * 4096
     t0 = time.time()
-    with multiprocessing.get_context("fork").Pool(8) as pool:
-        imgs = pool.map(synth.learned_image, range(nimg))
+    if nimg <= 8:   # few images (profiler runs): no worker processes
+        imgs = [synth.learned_image(i) for i in range(nimg)]
+    else:
+        with multiprocessing.get_context("fork").Pool(8) as pool:
+            imgs = pool.map(synth.learned_image, range(nimg))
     log(f"{nimg} images of 4096x4096 generated in {time.time() - t0:.1f}s")
     xs = [torch.from_numpy(im).to(dev) for im in imgs]
     del imgs

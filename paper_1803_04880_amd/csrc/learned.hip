@@ -16,7 +16,7 @@
 // (int8 MFMA, see correction_mfma), its output layer and the context on the
 // VALU; that is still ~60 operations per predicted sample against ~2 for the
 // plain predict, so this path is ALU-bound.  Protect and restore run one
-// fused kernel per level and direction (both 1-D passes of a 64 x 128 tile
+// fused kernel per level and direction (both 1-D passes of a 32 x 128 tile
 // in LDS, int16 samples, halos recomputed), so the only HBM traffic is each
 // level's input and output.  The training-pair capture keeps one kernel per
 // 1-D pass: a block takes SEG positions of LINES independent lines (rows: 1
@@ -434,9 +434,11 @@ hipError_t col_fwd(Src src, Sink sink, const Net &net, int N, int lines, const C
 // definition for any fragment contents, also those no protect produces.
 // Predicts go in batches of 64, one per lane, so that each wavefront calls
 // the matrix-core network with every lane active.
-// Ht is 64 in the forward and 32 in the inverse, whose int32 samples take
-// twice the LDS (its row halo adds loads, not predicts).
-constexpr int kFwdH = 64, kInvH = 32, kLvW = 128;
+// Ht is 32 in both directions: a taller forward tile recomputes fewer halo
+// rows in its row pass, but its LDS holds fewer blocks per compute unit, and
+// the wavefronts need the occupancy more (measured: 32 rows beat 48 and 64,
+// and in the inverse 16 and 48).
+constexpr int kFwdH = 32, kInvH = 32, kLvW = 128;
 constexpr int kLvPitch = kLvW + 16;  // local column q <-> c0 - 8 + q; local row k <-> r0 - 8 + k
 static_assert(kLvW == 128, "the row passes give each lane two columns of a 128-column tile");
 
