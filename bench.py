@@ -51,28 +51,35 @@ def percentile(xs, q):
 
 # sources of the kernels and launch planning the plain protect / restore runs
 PLAIN_PATH_SOURCES = ("api.hip", "common.h", "fwd.hip", "inv.hip", "lift.h", "pack.h")
+BATCH_PATH_SOURCES = PLAIN_PATH_SOURCES + ("batch.h", "batch.hip")
 
 
-def source_hash() -> str:
-    """Hash of the plain path's kernel sources; stored HBM-traffic figures are
+def source_hash(sources=PLAIN_PATH_SOURCES) -> str:
+    """Hash of the kernel sources of a path; stored HBM-traffic figures are
     only used while it matches the one recorded with them."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1803_04880_amd", "csrc")
-    for f in PLAIN_PATH_SOURCES:
+    for f in sources:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(workload_key: str):
+def stored_traffic(workload_key: str, sources=PLAIN_PATH_SOURCES):
+    """Counter-measured HBM bytes per launch of a workload's kernels, from
+    profiles/hbm_traffic.json, if recorded for the current sources (an entry
+    with its own source_hash, else the file's)."""
     path = os.path.join(PROFILES, "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("source_hash") != source_hash():
+    entry = rec.get(workload_key)
+    if not isinstance(entry, dict):
         return None
-    return rec.get(workload_key)
+    if entry.get("source_hash", rec.get("source_hash")) != source_hash(sources):
+        return None
+    return entry
 
 
 def _cpu_model() -> str:
@@ -293,7 +300,8 @@ def main():
     args = ap.parse_args()
 
     if args.print_source_hash:
-        print(source_hash())
+        print(source_hash())                      # plain path
+        print(source_hash(BATCH_PATH_SOURCES))    # batch path
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -747,6 +755,10 @@ def run_batch(args):
     torch.cuda.synchronize()
     ok &= all(bool(torch.equal(o, x)) for o, x in zip(b.outs, xs))
     alg = sum(s["n"] + 2 * (-(-s["n"] // s["width"])) * s["width"] for s in specs)  # per direction
+    # counter traffic is recorded for the default tile heights of the full
+    # batch (tuned heights vary with the tuner's timings)
+    traffic = (stored_traffic("batch_default_tiles", BATCH_PATH_SOURCES)
+               if args.no_tune and args.count == 2048 else None)
     avg_p, avg_r = sum(tp) / steps, sum(tr) / steps
     dom = "fwd_batch_kernel" if avg_p >= avg_r else "inv_batch_kernel"
     dom_ms = max(avg_p, avg_r)
@@ -768,7 +780,8 @@ def run_batch(args):
                   "restore_p50_ms": round(percentile(tr_e, 50), 3)},
         "roofline": {"bound": "hbm", "achieved": round(alg / (dom_ms * 1e-3) / 1e9, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(alg / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(alg / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": traffic.get(dom) if traffic else None,
                      "kernel": dom, "bytes_per_launch": alg, "avg_launch_ms": round(dom_ms, 3)},
         "cpu_baseline": None,
     }
