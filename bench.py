@@ -281,6 +281,9 @@ def main():
     ap.add_argument("--config", choices=["large", "small", "learned", "serve", "batch", "se8"],
                     default="large")
     ap.add_argument("--count", type=int, default=2048, help="batch config: number of buffers")
+    ap.add_argument("--batch-subset", default="",
+                    help="batch config, for counter runs: LEVELS,MIN_BYTES,MAX_ITEMS keeps only the "
+                         "buffers of that depth and at least that size, at most that many")
     ap.add_argument("--no-tune", action="store_true", help="batch config: default tile shapes")
     ap.add_argument("--duration", type=float, default=30.0, help="serve config: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve config: arrivals per second")
@@ -678,6 +681,9 @@ def run_batch(args):
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     specs = synth.batch_specs(args.count)
+    if args.batch_subset:
+        lv, min_n, most = (int(v) for v in args.batch_subset.split(","))
+        specs = [s for s in specs if s["levels"] == lv and s["n"] >= min_n][:most]
     t0 = time.time()
     xs = []
     with multiprocessing.get_context("fork").Pool(_host_cores()) as pool:
@@ -758,7 +764,7 @@ def run_batch(args):
     # counter traffic is recorded for the default tile heights of the full
     # batch (tuned heights vary with the tuner's timings)
     traffic = (stored_traffic("batch_default_tiles", BATCH_PATH_SOURCES)
-               if args.no_tune and args.count == 2048 else None)
+               if args.no_tune and args.count == 2048 and not args.batch_subset else None)
     avg_p, avg_r = sum(tp) / steps, sum(tr) / steps
     dom = "fwd_batch_kernel" if avg_p >= avg_r else "inv_batch_kernel"
     dom_ms = max(avg_p, avg_r)
@@ -771,7 +777,8 @@ def run_batch(args):
                                "1-4 levels, one persistent launch per direction replayed as HIP graphs, "
                                + ("default tile heights" if args.no_tune else
                                   "tile heights tuned per (width, levels) class"),
-                   "buffers": len(specs), "bytes": total, "classes": len(tune)},
+                   "buffers": len(specs), "bytes": total, "classes": len(tune),
+                   "subset": args.batch_subset or None},
         "bit_exact": ok,
         "latency_ms": {"protect_p50": round(percentile(tp, 50), 3),
                        "restore_p50": round(percentile(tr, 50), 3)},
