@@ -282,8 +282,9 @@ def main():
                     default="large")
     ap.add_argument("--count", type=int, default=2048, help="batch config: number of buffers")
     ap.add_argument("--batch-subset", default="",
-                    help="batch config, for counter runs: LEVELS,MIN_BYTES,MAX_ITEMS keeps only the "
-                         "buffers of that depth and at least that size, at most that many")
+                    help="batch config, for counter runs: LEVELS,MIN_BYTES,MAX_ITEMS[,KIND] keeps "
+                         "only the buffers of that depth and at least that size (and content kind: "
+                         "smooth, markov, uniform), at most that many")
     ap.add_argument("--no-tune", action="store_true", help="batch config: default tile shapes")
     ap.add_argument("--duration", type=float, default=30.0, help="serve config: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve config: arrivals per second")
@@ -682,8 +683,11 @@ def run_batch(args):
     dev = torch.device("cuda:0")
     specs = synth.batch_specs(args.count)
     if args.batch_subset:
-        lv, min_n, most = (int(v) for v in args.batch_subset.split(","))
-        specs = [s for s in specs if s["levels"] == lv and s["n"] >= min_n][:most]
+        fields = args.batch_subset.split(",")
+        lv, min_n, most = (int(v) for v in fields[:3])
+        kind = fields[3] if len(fields) > 3 else None
+        specs = [s for s in specs if s["levels"] == lv and s["n"] >= min_n
+                 and (kind is None or s["kind"] == kind)][:most]
     t0 = time.time()
     xs = []
     with multiprocessing.get_context("fork").Pool(_host_cores()) as pool:
