@@ -201,8 +201,12 @@ int dwtfrag_batch_create(const dwtfrag_item *items, uint32_t count,
 uint64_t dwtfrag_batch_device_bytes(const dwtfrag_batch *plan);
 
 /* Copy the plan's tables into `device_plan` (device, 256-byte aligned, at
- * least dwtfrag_batch_device_bytes) on `stream`, and wait for the copy.  The
- * buffer must stay allocated and untouched while the plan is used. */
+ * least dwtfrag_batch_device_bytes), asynchronously on `stream`: launches
+ * that use the plan must be ordered after it (the same stream, or a stream
+ * made to wait for this one).  The host tables the copies read stay with the
+ * plan; dwtfrag_batch_destroy waits for the last upload's copies before it
+ * frees them.  The buffer must stay allocated and untouched while the plan
+ * is used. */
 int dwtfrag_batch_upload(dwtfrag_batch *plan, void *device_plan, uint64_t device_bytes,
                          void *stream);
 
@@ -211,6 +215,7 @@ int dwtfrag_batch_upload(dwtfrag_batch *plan, void *device_plan, uint64_t device
 int dwtfrag_batch_protect(const dwtfrag_batch *plan, void *stream);
 int dwtfrag_batch_restore(const dwtfrag_batch *plan, void *stream);
 
+/* Free a plan (NULL is a no-op); waits for its last upload's copies. */
 void dwtfrag_batch_destroy(dwtfrag_batch *plan);
 
 /* Autotuner: time protect + restore of one buffer (device `in`, n bytes)

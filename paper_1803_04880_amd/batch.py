@@ -135,16 +135,28 @@ class Batch:
         self._h = handle
         nbytes = int(lib().dwtfrag_batch_device_bytes(handle))
         self.plan = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        # the upload is asynchronous on the current stream
+        self._upload_stream = torch.cuda.current_stream(dev)
         rc = lib().dwtfrag_batch_upload(handle, self.plan.data_ptr(), nbytes, _stream(None))
         if rc != DWTFRAG_OK:
             raise DwtfragError(rc, "dwtfrag_batch_upload")
 
+    def _after_upload(self, stream):
+        """Order a launch on `stream` after the plan's upload.  Under HIP graph
+        capture on another stream the caller orders the two (a capture cannot
+        wait for work outside it)."""
+        s = stream if stream is not None else torch.cuda.current_stream(self.plan.device)
+        if s != self._upload_stream and not torch.cuda.is_current_stream_capturing():
+            s.wait_stream(self._upload_stream)
+
     def protect(self, stream=None):
+        self._after_upload(stream)
         rc = lib().dwtfrag_batch_protect(self._h, _stream(stream))
         if rc != DWTFRAG_OK:
             raise DwtfragError(rc, "dwtfrag_batch_protect")
 
     def restore(self, stream=None):
+        self._after_upload(stream)
         rc = lib().dwtfrag_batch_restore(self._h, _stream(stream))
         if rc != DWTFRAG_OK:
             raise DwtfragError(rc, "dwtfrag_batch_restore")

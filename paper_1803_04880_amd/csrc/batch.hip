@@ -43,6 +43,7 @@ struct dwtfrag_batch {
   int fwd_blocks = 0, inv_blocks = 0;      // persistent grid per direction
   uint64_t off_ctr = 0, off_items = 0, off_tiles = 0, bytes = 0;
   char *dev = nullptr;                     // caller's device copy, set by upload
+  hipEvent_t uploaded = nullptr;           // the last upload's copies are done
 };
 
 namespace {
@@ -165,8 +166,10 @@ int dwtfrag_batch_upload(dwtfrag_batch *b, void *device_plan, uint64_t device_by
   if (device_bytes < b->bytes) return DWTFRAG_EWORKSPACE;
   char *dev = static_cast<char *>(device_plan);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  // pageable sources: the copies are staged before the calls return; the
-  // queue counters start at zero (the kernels leave them at zero)
+  // The copies run asynchronously on the stream: their sources (the zero
+  // counters below, the plan's own tables) stay in place until
+  // dwtfrag_batch_destroy, which waits for the event recorded behind them.
+  // The queue counters start at zero (the kernels leave them at zero).
   static const BatchCounters zero[2] = {};
   if (hipMemcpyAsync(dev + b->off_ctr, zero, sizeof(zero), hipMemcpyHostToDevice, st) != hipSuccess)
     return DWTFRAG_EDEVICE;
@@ -177,7 +180,11 @@ int dwtfrag_batch_upload(dwtfrag_batch *b, void *device_plan, uint64_t device_by
       hipMemcpyAsync(dev + b->off_tiles, b->tiles.data(), b->tiles.size() * sizeof(int2),
                      hipMemcpyHostToDevice, st) != hipSuccess)
     return DWTFRAG_EDEVICE;
-  if (hipStreamSynchronize(st) != hipSuccess) return DWTFRAG_EDEVICE;
+  if (!b->uploaded && hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess) {
+    b->uploaded = nullptr;
+    return DWTFRAG_EDEVICE;
+  }
+  if (hipEventRecord(b->uploaded, st) != hipSuccess) return DWTFRAG_EDEVICE;
   b->dev = dev;
   return DWTFRAG_OK;
 }
@@ -208,6 +215,13 @@ int dwtfrag_batch_restore(const dwtfrag_batch *b, void *stream) {
   return DWTFRAG_OK;
 }
 
-void dwtfrag_batch_destroy(dwtfrag_batch *b) { delete b; }
+void dwtfrag_batch_destroy(dwtfrag_batch *b) {
+  if (!b) return;
+  if (b->uploaded) {  // the copies read the plan's tables until then
+    hipEventSynchronize(b->uploaded);
+    hipEventDestroy(b->uploaded);
+  }
+  delete b;
+}
 
 }  // extern "C"

@@ -132,10 +132,9 @@ class Server:
         planned = self._now()
         batches = []
         with torch.cuda.stream(stream):
-            # Both plans are built and uploaded before either batch is
-            # launched: an upload waits for the work already queued on its
-            # stream, which at this point is only retired work (a stream is
-            # free only once its previous launch has retired).
+            # Both plans are built and uploaded (asynchronous copies on this
+            # stream) before either batch is launched on the same stream; the
+            # host does not wait for the device here.
             pb = rb = None
             if prot:
                 pb = Batch([r.x for r in prot], [r.width for r in prot], [r.levels for r in prot],
