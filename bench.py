@@ -288,6 +288,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="batch config: default tile shapes")
     ap.add_argument("--duration", type=float, default=30.0, help="serve config: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve config: arrivals per second")
+    ap.add_argument("--learned-streams", type=int, default=16,
+                    help="learned config: streams the per-image calls are spread over")
     ap.add_argument("--images", type=int, default=0,
                     help="learned config: number of 4096x4096 images (default 64)")
     ap.add_argument("--seg-rows", type=int, default=0)
@@ -934,6 +936,8 @@ def run_learned(args):
     steps = args.steps if args.steps != 50 else 10
     warmup = args.warmup if args.warmup != 5 else 2
     nimg = args.images or synth.LEARNED_IMAGES
+    if args.learned_streams < 1:
+        raise SystemExit("--learned-streams must be at least 1")
     W, L, n = 4096, 3, 4096 * 4096
     t0 = time.time()
     if nimg <= 8:   # few images (profiler runs): no worker processes
@@ -952,13 +956,14 @@ def run_learned(args):
     privs = [torch.empty(g["priv_bytes"], dtype=torch.uint8, device=dev) for _ in range(nimg)]
     pubs = [torch.empty(g["pub_bytes"] // 2, dtype=torch.int16, device=dev) for _ in range(nimg)]
     outs = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(nimg)]
-    # The images are independent calls: they go round-robin to four streams
-    # (default priority), each with its own workspace, forked from and
+    # The images are independent calls: they go round-robin to a few streams
+    # (--learned-streams, sixteen by default; all at the default priority),
+    # each with its own workspace, forked from and
     # joined back into the current stream, so that one image's small levels
     # overlap another's large one.  Image i's restore runs on the stream of
     # its protect.
     main = torch.cuda.current_stream()
-    n_streams = 4
+    n_streams = args.learned_streams
     side = [torch.cuda.Stream(device=dev) for _ in range(n_streams)]
     wss = [GL.workspace(n, W, L, dev) for _ in range(n_streams)]
 
@@ -1077,7 +1082,7 @@ def run_learned(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "int8/int32", "data": "synthetic",
         "config": {"workload": f"{nimg} smooth 4096x4096 images ({total / 2**30:.2f} GiB), 3 levels, "
                                "context network trained by the oracle", "images": nimg,
-                   "width": W, "levels": L},
+                   "width": W, "levels": L, "streams": n_streams},
         "bit_exact": bool(bit_exact),
         "latency_us": {"protect_all_p50": round(percentile(tp, 50), 1),
                        "restore_all_p50": round(percentile(tr, 50), 1)},
