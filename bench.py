@@ -7,9 +7,12 @@ A step is one pass of the whole hot path over the workload: protect (view,
 inverse lifting, byte store), inputs resident in HBM.  Prints one JSON line.
 
 value      = n * K / (sum of the K protect and K restore launch durations),
-             each launch started cache-cold (a 1 GiB buffer is overwritten
-             before each direction, outside the events)   [GB/s of user bytes]
+             each launch started cache-cold with clean caches (a 1 GiB buffer
+             is overwritten and read back before each direction, outside the
+             events)                                      [GB/s of user bytes]
              (512 x 512 workload: n * K / wall time of K warm steps)
+cold_dirty = the same with the overwrite alone: the caches then hold 1 GiB of
+             dirty lines, whose write-back lands inside the timed launch
 warm       = the same K steps back to back, value = n * K / wall time
 roofline   = algorithmic bytes per launch (n + 2*H*W: read the bytes, write
              the int16 fragments; restore reads them back and writes bytes)
@@ -387,21 +390,31 @@ def main():
     stream = torch.cuda.current_stream()
     alg_bytes = n + 2 * H * width  # per launch, each direction
 
-    def run_steps(cold: bool):
-        """K steps; cold: a 1 GiB scratch buffer is overwritten (outside the
-        events) before each direction, so every launch starts with the
-        Infinity Cache and the L2s holding none of its data."""
+    scratch = None
+    evict_sum = torch.zeros((), dtype=torch.int64, device=dev)
+
+    def evict(clean: bool, k: int):
+        """Outside the events: overwrite a 1 GiB scratch buffer, so the
+        Infinity Cache and the L2s hold none of the workload's data; clean:
+        then read it back, so they hold no dirty lines either (otherwise the
+        write-back of the fill's 1 GiB lands inside the next timed launch)."""
+        scratch.fill_(k & 255)
+        if clean:
+            evict_sum.add_(scratch.view(torch.int64).sum())
+
+    def run_steps(cold: bool, clean: bool = True):
+        """K steps; cold: evict(clean) before each direction."""
         ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
         torch.cuda.synchronize()
         w0 = time.perf_counter()
         for k in range(args.steps):
             if cold:
-                scratch.fill_(2 * k + 1)
+                evict(clean, 2 * k + 1)
             ev[k][0].record(stream)
             protect()
             ev[k][1].record(stream)
             if cold:
-                scratch.fill_(2 * k + 2)
+                evict(clean, 2 * k + 2)
             ev[k][2].record(stream)
             restore()
             ev[k][3].record(stream)
@@ -425,15 +438,19 @@ def main():
                      "pair_p99": round(percentile(tpair, 99), 1)},
             avg_us={"protect": round(avg_p, 2), "restore": round(avg_r, 2)})
 
-    # headline of the 256 MiB workload: cache-cold steps, value = n * K / (sum
-    # of the protect and restore launch durations), warm back-to-back steps
-    # as a footnote.  The 512 x 512 workload is a latency measurement of
-    # data that stays in the caches: warm steps, value = n * K / wall time.
+    # headline of the 256 MiB workload: cache-cold steps (clean caches), value
+    # = n * K / (sum of the protect and restore launch durations); cold steps
+    # behind a fill alone (dirty caches) and warm back-to-back steps as
+    # footnotes.  The 512 x 512 workload is a latency measurement of data
+    # that stays in the caches: warm steps, value = n * K / wall time.
     warm = run_steps(False)
+    cold_dirty = None
     if args.config == "large":
         scratch = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        evict(True, 0)  # the reduction's first call sets itself up (host time)
+        torch.cuda.synchronize()
         cold = run_steps(True)
-        del scratch
+        cold_dirty = run_steps(True, clean=False)
         value = n * args.steps / (cold["busy_us"] * 1e-6) / 1e9
     else:
         cold = dict(warm, busy_us=warm["wall"] * 1e6)
@@ -446,7 +463,9 @@ def main():
                 "avg_launch_us": round(cold["dom_us"], 2)}
 
     # context for the HBM fraction: the rate of a plain device copy of the
-    # same n bytes (read n, write n) on this GPU, timed the same way
+    # same n bytes (read n, write n) on this GPU, timed the same way as the
+    # headline launches (cold, clean caches: one event pair per copy), and
+    # back to back as well
     spare = torch.empty_like(x)
     spare.copy_(x)
     c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -455,10 +474,29 @@ def main():
         spare.copy_(x)
     c1.record(stream)
     torch.cuda.synchronize()
-    copy_us = c0.elapsed_time(c1) * 1e3 / 20
+    copy_warm_us = c0.elapsed_time(c1) * 1e3 / 20
+    copy_us = copy_dirty_us = copy_warm_us
+
+    def cold_copies(clean: bool) -> float:
+        cev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(20)]
+        for k in range(20):
+            evict(clean, k)
+            cev[k][0].record(stream)
+            spare.copy_(x)
+            cev[k][1].record(stream)
+        torch.cuda.synchronize()
+        return sum(a.elapsed_time(b) for a, b in cev) * 1e3 / 20
+
+    if scratch is not None:
+        copy_us = cold_copies(True)
+        copy_dirty_us = cold_copies(False)
+        del scratch
     del spare
     copy_gbps = 2 * n / (copy_us * 1e-6) / 1e9
     device_copy = {"us": round(copy_us, 1), "gbps": round(copy_gbps, 1),
+                   "cache": "as the headline launches",
+                   "cold_dirty_gbps": round(2 * n / (copy_dirty_us * 1e-6) / 1e9, 1),
+                   "warm_back_to_back_gbps": round(2 * n / (copy_warm_us * 1e-6) / 1e9, 1),
                    "dominant_kernel_frac_of_copy": round(cold["achieved"] / copy_gbps, 4)}
 
     result = {
@@ -476,7 +514,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["name"], "n_bytes": n, "rows": H, "width": width,
                    "levels": levels,
-                   "cache": ("cold (1 GiB overwritten before each direction)"
+                   "cache": ("cold (1 GiB overwritten, then read back, before each direction)"
                              if args.config == "large" else "warm (back to back)"),
                    "launch": {"seg_rows": args.seg_rows, "lane_cols": args.lane_cols}},
         "bit_exact": bit_exact,
@@ -493,6 +531,13 @@ def main():
         "device_copy": device_copy,
         "cpu_baseline": None,
     }
+    if cold_dirty is not None:
+        result["cold_dirty"] = {
+            "value": round(n * args.steps / (cold_dirty["busy_us"] * 1e-6) / 1e9, 2),
+            "latency_us": cold_dirty["latency"], "avg_launch_us": cold_dirty["avg_us"],
+            "roofline_frac": round(cold_dirty["achieved"] / HBM_PEAK_GBS, 4),
+            "note": "1 GiB overwritten (not read back) before each direction: the caches hold "
+                    "1 GiB of dirty lines, whose write-back falls inside the timed launch"}
     if args.config == "large" and not args.no_small:
         result["small_latency_us"] = small_latency(dev, stream)
     if not args.no_cpu_baseline and args.config == "large":
