@@ -477,19 +477,37 @@ def main():
     copy_warm_us = c0.elapsed_time(c1) * 1e3 / 20
     copy_us = copy_dirty_us = copy_warm_us
 
-    def cold_copies(clean: bool) -> float:
+    def cold_copies(clean: bool, op=lambda: spare.copy_(x)) -> float:
         cev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(20)]
         for k in range(20):
             evict(clean, k)
             cev[k][0].record(stream)
-            spare.copy_(x)
+            op()
             cev[k][1].record(stream)
         torch.cuda.synchronize()
         return sum(a.elapsed_time(b) for a, b in cev) * 1e3 / 20
 
+    shaped = None
     if scratch is not None:
         copy_us = cold_copies(True)
         copy_dirty_us = cold_copies(False)
+        # the library's reference streams: the same bytes as the forward
+        # (widen: read n, write 2n) and the inverse (narrow: read 2n, write
+        # n) in one-shot launches, timed as the headline launches
+        wide = torch.empty(n, dtype=torch.int16, device=dev)
+        dwtfrag.ref_widen(x, wide)
+        dwtfrag.ref_narrow(wide, spare)
+        torch.cuda.synchronize()
+        assert torch.equal(spare, x), "reference streams do not round trip"
+        widen_us = cold_copies(True, lambda: dwtfrag.ref_widen(x, wide))
+        narrow_us = cold_copies(True, lambda: dwtfrag.ref_narrow(wide, spare))
+        del wide
+        like = widen_us if cold["dominant"] == "fwd_kernel" else narrow_us
+        shaped = {"widen_u8_to_i16": {"us": round(widen_us, 1),
+                                      "gbps": round(alg_bytes / (widen_us * 1e-6) / 1e9, 1)},
+                  "narrow_i16_to_u8": {"us": round(narrow_us, 1),
+                                       "gbps": round(alg_bytes / (narrow_us * 1e-6) / 1e9, 1)},
+                  "dominant_kernel_frac_of_same_shape": round(like / cold["dom_us"], 4)}
         del scratch
     del spare
     copy_gbps = 2 * n / (copy_us * 1e-6) / 1e9
@@ -498,6 +516,8 @@ def main():
                    "cold_dirty_gbps": round(2 * n / (copy_dirty_us * 1e-6) / 1e9, 1),
                    "warm_back_to_back_gbps": round(2 * n / (copy_warm_us * 1e-6) / 1e9, 1),
                    "dominant_kernel_frac_of_copy": round(cold["achieved"] / copy_gbps, 4)}
+    if shaped is not None:
+        device_copy["same_traffic_shape"] = shaped
 
     result = {
         "metric": "protect+restore GB/s on 1 MI355X (% HBM roofline), bit-exact; p50/p99 latency",

@@ -375,6 +375,20 @@ int dwtfrag_se8_restore(const uint8_t *priv, const uint8_t *pub1, const uint8_t 
                         uint64_t n, uint32_t width, const uint8_t key[16],
                         const uint8_t nonce[16], uint8_t *out, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Reference streams, for measurement context only (not part of the method;
+ * for callers that compare the lifting kernels with the plainest kernel of
+ * the same traffic): one-shot launches that move the same bytes as the
+ * forward and the inverse of a whole buffer.
+ *   widen:  out[i] = in[i] zero-extended to int16   (reads n, writes 2n bytes)
+ *   narrow: out[i] = low byte of in[i]              (reads 2n, writes n bytes)
+ * in, out: device, not overlapping, 16-byte aligned; n a positive multiple of
+ * 16 below 2^43.  DWTFRAG_EINVAL otherwise; DWTFRAG_EDEVICE if the launch
+ * fails.  Asynchronous on stream.
+ * ------------------------------------------------------------------------ */
+int dwtfrag_ref_widen(const uint8_t *in, int16_t *out, uint64_t n, void *stream);
+int dwtfrag_ref_narrow(const int16_t *in, uint8_t *out, uint64_t n, void *stream);
+
 /* Static text for a status code. */
 const char *dwtfrag_strerror(int code);
 

@@ -63,7 +63,8 @@ EXPORTS = ("dwtfrag_geometry", "dwtfrag_default_width", "dwtfrag_protect",
            "dwtfrag_batch_create", "dwtfrag_batch_device_bytes", "dwtfrag_batch_upload",
            "dwtfrag_batch_protect", "dwtfrag_batch_restore", "dwtfrag_batch_destroy",
            "dwtfrag_autotune",
-           "dwtfrag_se8_geometry", "dwtfrag_se8_protect", "dwtfrag_se8_restore")
+           "dwtfrag_se8_geometry", "dwtfrag_se8_protect", "dwtfrag_se8_restore",
+           "dwtfrag_ref_widen", "dwtfrag_ref_narrow")
 
 
 def lib():
@@ -127,6 +128,9 @@ def lib():
     L.dwtfrag_se8_protect.argtypes = [vp, u64, u32, cp, cp, vp, vp, vp, vp]
     L.dwtfrag_se8_restore.argtypes = [vp, vp, vp, u64, u32, cp, cp, vp, vp]
     for f in ("dwtfrag_se8_geometry", "dwtfrag_se8_protect", "dwtfrag_se8_restore"):
+        getattr(L, f).restype = ctypes.c_int
+    for f in ("dwtfrag_ref_widen", "dwtfrag_ref_narrow"):
+        getattr(L, f).argtypes = [vp, vp, u64, vp]
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -268,6 +272,32 @@ def aes128_ctr(x: torch.Tensor, key: bytes, nonce: bytes, first_block: int = 0, 
                                   _key16(nonce, "nonce"), first_block, _stream(stream))
     if rc != DWTFRAG_OK:
         raise DwtfragError(rc, "dwtfrag_aes128_ctr")
+    return out
+
+
+def ref_widen(x: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """Reference stream (measurement context, not the method): out = x as
+    int16, one-shot, the forward's traffic (read n bytes, write 2n)."""
+    _check_dev(x, torch.uint8, "x")
+    _check_dev(out, torch.int16, "out")
+    if out.numel() != x.numel():
+        raise ValueError("out must hold x.numel() int16 values")
+    rc = lib().dwtfrag_ref_widen(x.data_ptr(), out.data_ptr(), x.numel(), _stream(stream))
+    if rc != DWTFRAG_OK:
+        raise DwtfragError(rc, "dwtfrag_ref_widen")
+    return out
+
+
+def ref_narrow(x: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """Reference stream (measurement context, not the method): out = low
+    bytes of the int16 x, one-shot, the inverse's traffic (read 2n, write n)."""
+    _check_dev(x, torch.int16, "x")
+    _check_dev(out, torch.uint8, "out")
+    if out.numel() != x.numel():
+        raise ValueError("out must hold x.numel() bytes")
+    rc = lib().dwtfrag_ref_narrow(x.data_ptr(), out.data_ptr(), x.numel(), _stream(stream))
+    if rc != DWTFRAG_OK:
+        raise DwtfragError(rc, "dwtfrag_ref_narrow")
     return out
 
 

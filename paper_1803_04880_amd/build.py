@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdwtfrag.so")
-SOURCES = ["api.hip", "batch.hip", "fwd.hip", "inv.hip", "ctr.hip", "learned.hip", "se8.hip"]
+SOURCES = ["api.hip", "batch.hip", "fwd.hip", "inv.hip", "ctr.hip", "learned.hip", "se8.hip",
+           "refstream.hip"]
 ARCH = os.environ.get("DWTFRAG_ARCH", "gfx950")
 # Per-source compiler options: the SHA-2 compressions of se8.hip are fully
 # unrolled loops (their message schedule lives in registers only when every
