@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void ref_narrow_kernel(const int16_t *__restri
 namespace {
 
 bool ref_args_ok(const void *a, const void *b, uint64_t n) {
-  return a && b && n && n % 16 == 0 && n / 16 / 256 < (1ull << 31) &&
+  return a && b && n && n % 16 == 0 && (n / 16 + 255) / 256 < (1ull << 31) &&
          ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0;
 }
 
