@@ -26,8 +26,10 @@ cpu_baseline = the CPU oracle on a bounded sample of the same workload, over
 from __future__ import annotations
 
 import argparse
+import contextlib
 import hashlib
 import json
+import multiprocessing
 import os
 import sys
 import time
@@ -41,6 +43,20 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+@contextlib.contextmanager
+def _closing_pool(processes: int):
+    """A fork pool whose workers leave by finishing their queue (close and
+    join) rather than by SIGTERM (a plain `with Pool()` terminates them):
+    under a profiler that traps signals in every process, a terminated worker
+    can hang in the profiler's handler and the join with it."""
+    pool = multiprocessing.get_context("fork").Pool(processes)
+    try:
+        yield pool
+    finally:
+        pool.close()
+        pool.join()
 
 
 def percentile(xs, q):
@@ -245,7 +261,7 @@ def cpu_baseline(cfg, rows: int = 2048, row0: int = 2048):
     _shared_i64("a", cells)
     _shared_i64("b", cells)
     _shared_i64("ctr", -(-2 * cells // 8) + 2)
-    with multiprocessing.get_context("fork").Pool(cores) as pool:
+    with _closing_pool(cores) as pool:
         pool.map(_rows_task, [("a", "b", 1, 1, 0, 1, False)] * cores)  # workers up
         t0 = time.perf_counter()
         ppriv, ppub, pback = _pool_protect_restore(pool, cores, sample, w, lv, key, nonce)
@@ -757,7 +773,7 @@ def run_batch(args):
                  and (kind is None or s["kind"] == kind)][:most]
     t0 = time.time()
     xs = []
-    with multiprocessing.get_context("fork").Pool(_host_cores()) as pool:
+    with _closing_pool(_host_cores()) as pool:
         for buf in pool.imap(_batch_item, specs, chunksize=4):
             xs.append(torch.from_numpy(buf).to(dev))
     total = sum(s["n"] for s in specs)
@@ -1008,7 +1024,7 @@ def run_learned(args):
     if nimg <= 8:   # few images (profiler runs): no worker processes
         imgs = [synth.learned_image(i) for i in range(nimg)]
     else:
-        with multiprocessing.get_context("fork").Pool(8) as pool:
+        with _closing_pool(8) as pool:
             imgs = pool.map(synth.learned_image, range(nimg))
     log(f"{nimg} images of 4096x4096 generated in {time.time() - t0:.1f}s")
     xs = [torch.from_numpy(im).to(dev) for im in imgs]

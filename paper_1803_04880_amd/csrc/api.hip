@@ -20,6 +20,9 @@ hipError_t launch_ctr(const uint8_t *in, uint8_t *out, uint64_t nbytes, const Ae
                       uint64_t first_block, hipStream_t s);
 int fwd_waves_per_cu(int L, int C1, bool u8in);
 int inv_waves_per_cu(int L, int C1, bool u8out);
+int inv_split_waves_per_cu(int L, int C1, bool all_fast);
+bool inv_stage_split_ok(const StageParams &P);
+bool inv_stage_all_fast(const StageParams &P, int L, int C1);
 
 static constexpr AesTables kHostTables = make_aes_tables();
 
@@ -121,13 +124,15 @@ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 // Wavefronts the current device keeps resident at once for the kernel of a
 // stage: compute units x resident wavefronts per CU (queried once per device
-// and kernel variant; falls back to 256 x 16 if the queries fail).
-int64_t device_slots(bool forward, int L, int C1, bool bytes) {
-  constexpr int kDev = 16, kVar = 2 * 5 * 2 * 2;
+// and kernel variant; falls back to 256 x 16 if the queries fail).  split:
+// 0 for the one-launch kernels, 1 / 2 for the split restore's packed kernel
+// with every wavefront FAST / not.
+int64_t device_slots(bool forward, int L, int C1, bool bytes, int split = 0) {
+  constexpr int kDev = 16, kVar = 2 * 5 * 3 * 2 * 2;
   static std::atomic<int> cache[kDev][kVar];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDev) dev = -1;
-  const int var = ((forward ? 1 : 0) * 5 + L) * 4 + (C1 == 16 ? 2 : 0) + (bytes ? 1 : 0);
+  const int var = (((forward ? 1 : 0) * 5 + L) * 3 + split) * 4 + (C1 == 16 ? 2 : 0) + (bytes ? 1 : 0);
   if (dev >= 0) {
     const int v = cache[dev][var].load(std::memory_order_relaxed);
     if (v > 0) return v;
@@ -135,7 +140,9 @@ int64_t device_slots(bool forward, int L, int C1, bool bytes) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev < 0 ? 0 : dev) != hipSuccess)
     cus = 0;
-  const int per_cu = forward ? fwd_waves_per_cu(L, C1, bytes) : inv_waves_per_cu(L, C1, bytes);
+  const int per_cu = forward ? fwd_waves_per_cu(L, C1, bytes)
+                     : split ? inv_split_waves_per_cu(L, C1, split == 1)
+                             : inv_waves_per_cu(L, C1, bytes);
   const int slots = (cus > 0 && per_cu > 0) ? cus * per_cu : 256 * 16;
   if (dev >= 0) cache[dev][var].store(slots, std::memory_order_relaxed);
   return slots;
@@ -222,10 +229,24 @@ int plan_stage(const Geometry &g, int s, bool forward, const dwtfrag_launch *lau
     // A launch of its own whose grid stays within one wavefront per SIMD
     // even at one unit per segment takes one unit per segment: the extra
     // halo rows run on otherwise idle SIMDs and each stream is shorter.
-    const int64_t slots = device_slots(forward, L, C1, s == 0);
-    n_seg = std::max<int64_t>(1, slots / P->n_win);
+    // A restore's byte stage that runs as the split pair is filled to the
+    // packed kernel's own residency (three wavefronts per SIMD at 16
+    // columns, where the one-launch kernel holds two: 256 MiB at three
+    // levels, restore 210 -> 195 us), and planned again with the one-launch
+    // kernel's when the finished plan turns out not to run split.
     const int min_units = (alone && int64_t(P->units) * P->n_win <= device_simds()) ? 1 : 2;
-    n_seg = std::min<int64_t>(n_seg, std::max(1, P->units / min_units));
+    const auto segments = [&](int split) {
+      const int64_t slots = device_slots(forward, L, C1, s == 0, split);
+      const int64_t k = std::max<int64_t>(1, slots / P->n_win);
+      return std::min<int64_t>(k, std::max(1, P->units / min_units));
+    };
+    const int split = (alone && !forward && s == 0 && P->n_valid >= (int64_t(1) << 24))
+                          ? (inv_stage_all_fast(*P, L, C1) ? 1 : 2) : 0;
+    n_seg = segments(split);
+    if (split) {
+      P->n_seg = int32_t(std::min<int64_t>(n_seg, P->units));
+      if (!inv_stage_split_ok(*P)) n_seg = segments(0);
+    }
   }
   P->n_seg = int32_t(std::min<int64_t>(std::max<int64_t>(n_seg, 1), P->units));
   const int64_t waves = int64_t(P->n_win) * P->n_seg;

@@ -892,6 +892,31 @@ int inv_waves_per_cu(int L, int C1, bool u8out) {
   return blocks * kWavesPerBlock;
 }
 
+// The split restore for the planner: whether a byte-output stage runs as
+// the split pair, whether all its wavefronts are FAST (the packed kernel's
+// variant), and that variant's resident wavefronts per compute unit.
+bool inv_stage_split_ok(const StageParams &P) { return inv_split_ok(P); }
+bool inv_stage_all_fast(const StageParams &P, int L, int C1) { return inv_all_fast(P, L, C1); }
+
+template <int L, int C1, bool ALL_FAST>
+static const void *inv_split_fn() {
+  if constexpr (C1 == 8) return reinterpret_cast<const void *>(&inv_split_pk8<L, ALL_FAST>);
+  else return reinterpret_cast<const void *>(&inv_split_pk16<L, ALL_FAST>);
+}
+
+int inv_split_waves_per_cu(int L, int C1, bool all_fast) {
+  const void *fn = nullptr;
+#define DWTFRAG_FN(LL, CC) \
+  if (L == LL && C1 == CC) fn = all_fast ? inv_split_fn<LL, CC, true>() : inv_split_fn<LL, CC, false>();
+  DWTFRAG_FN(1, 8) DWTFRAG_FN(2, 8) DWTFRAG_FN(3, 8)
+  DWTFRAG_FN(1, 16) DWTFRAG_FN(2, 16) DWTFRAG_FN(3, 16) DWTFRAG_FN(4, 16)
+#undef DWTFRAG_FN
+  int blocks = 0;
+  if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kBlockThreads, 0) != hipSuccess)
+    return 0;
+  return blocks * kWavesPerBlock;
+}
+
 hipError_t launch_inv(int L, int C1, bool u8out, const int16_t *llin, const int16_t *pub,
                       void *out, const StageParams &P, hipStream_t s) {
   const bool split = u8out && inv_split_ok(P);

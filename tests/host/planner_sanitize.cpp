@@ -25,6 +25,9 @@ hipError_t launch_inv_batch(const BatchItem *, const int2 *, int64_t, BatchCount
                             hipStream_t) { return hipErrorInvalidValue; }
 int fwd_waves_per_cu(int L, int C1, bool) { return C1 == 16 ? 8 : 12 + L % 2; }
 int inv_waves_per_cu(int L, int C1, bool) { return C1 == 16 ? 8 : 16 - L % 2; }
+int inv_split_waves_per_cu(int L, int C1, bool all_fast) { return C1 == 16 ? 12 - !all_fast : 16 - L % 2; }
+bool inv_stage_split_ok(const StageParams &P) { return P.n_valid >= (int64_t(1) << 24) && P.n_seg > 1; }
+bool inv_stage_all_fast(const StageParams &P, int, int C1) { return P.W % C1 == 0; }
 int fwd_batch_blocks_per_cu() { return 2; }
 int inv_batch_blocks_per_cu() { return 2; }
 }  // namespace dwtfrag
