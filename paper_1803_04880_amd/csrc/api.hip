@@ -6,7 +6,6 @@
 #include <atomic>
 #include <cstring>
 #include <mutex>
-#include <vector>
 
 #include "common.h"
 
@@ -66,19 +65,25 @@ constexpr uint64_t kMaxDim = 0x7FFF0000ull;
 // Bytes of the static workspace behind dwtfrag_protect_noalloc (16 MiB).
 constexpr uint64_t kScratchBytes = uint64_t(16) << 20;
 
+// Deepest decomposition accepted, and the fused stages it takes.  Geometry and
+// launch plans live in fixed arrays of these sizes, so planning a call
+// allocates nothing, on the host or the device.
+constexpr uint32_t kMaxLevels = 32;
+constexpr int kMaxStages = int((kMaxLevels + kMaxFused - 1) / kMaxFused);
+
 struct Geometry {
   uint64_t n;
   uint32_t W, H, levels;
-  std::vector<uint64_t> h, w;  // level dims 0..levels
+  uint64_t h[kMaxLevels + 1], w[kMaxLevels + 1];  // level dims 0..levels
   uint64_t priv_bytes, pub_bytes, ws_bytes;
-  std::vector<uint64_t> ws_off;  // workspace byte offset of LL_{4(s+1)}, s = 0..stages-2
+  uint64_t ws_off[kMaxStages];  // workspace byte offset of LL_{4(s+1)}, s = 0..stages-2
   int stages;
 };
 
 uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
 
 int make_geometry(uint64_t n, uint32_t width, uint32_t levels, Geometry *g) {
-  if (n == 0 || width == 0 || levels == 0 || levels > 32) return DWTFRAG_EINVAL;
+  if (n == 0 || width == 0 || levels == 0 || levels > kMaxLevels) return DWTFRAG_EINVAL;
   if (width > kMaxDim) return DWTFRAG_ERANGE;
   const uint64_t H = (n + width - 1) / width;
   if (H > kMaxDim) return DWTFRAG_ERANGE;
@@ -87,8 +92,9 @@ int make_geometry(uint64_t n, uint32_t width, uint32_t levels, Geometry *g) {
   g->W = width;
   g->H = uint32_t(H);
   g->levels = levels;
-  g->h.assign(levels + 1, 0);
-  g->w.assign(levels + 1, 0);
+  std::memset(g->h, 0, sizeof(g->h));
+  std::memset(g->w, 0, sizeof(g->w));
+  std::memset(g->ws_off, 0, sizeof(g->ws_off));
   g->h[0] = H;
   g->w[0] = width;
   for (uint32_t l = 1; l <= levels; ++l) {
@@ -99,10 +105,9 @@ int make_geometry(uint64_t n, uint32_t width, uint32_t levels, Geometry *g) {
   g->priv_bytes = 2 * ll;
   g->pub_bytes = 2 * (H * width - ll);
   g->stages = int((levels + kMaxFused - 1) / kMaxFused);
-  g->ws_off.clear();
   uint64_t ws = 0;
   for (int s = 0; s + 1 < g->stages; ++s) {
-    g->ws_off.push_back(ws);
+    g->ws_off[s] = ws;
     const int lv = kMaxFused * (s + 1);
     ws += align256(2 * g->h[lv] * g->w[lv]);
   }
@@ -293,8 +298,8 @@ int protect_planned(const Geometry &g, const uint8_t *in, const uint8_t key[16],
     return DWTFRAG_EINVAL;
   AesKey k;
   expand_key(key, nonce, &k);
-  std::vector<StageParams> plans(g.stages);
-  std::vector<int> Ls(g.stages), C1s(g.stages);
+  StageParams plans[kMaxStages];
+  int Ls[kMaxStages], C1s[kMaxStages];
   for (int s = 0; s < g.stages; ++s) {
     const int rc = plan_stage(g, s, true, launch, k, &plans[s], &Ls[s], &C1s[s], true);
     if (rc != DWTFRAG_OK) return rc;
@@ -412,8 +417,8 @@ int dwtfrag_restore(const uint8_t *priv, const int16_t *pub, uint64_t n, uint32_
     return DWTFRAG_EINVAL;
   AesKey k;
   expand_key(key, nonce, &k);
-  std::vector<StageParams> plans(g.stages);
-  std::vector<int> Ls(g.stages), C1s(g.stages);
+  StageParams plans[kMaxStages];
+  int Ls[kMaxStages], C1s[kMaxStages];
   for (int s = 0; s < g.stages; ++s) {
     rc = plan_stage(g, s, false, launch, k, &plans[s], &Ls[s], &C1s[s], true);
     if (rc != DWTFRAG_OK) return rc;
