@@ -330,8 +330,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(each buffer is independent; see the design notes on sharding).",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(buffers are independent, so several GPUs would each take whole buffers).",
               file=sys.stderr)
         sys.exit(2)
 
